@@ -1,0 +1,311 @@
+/*
+ * Reference (oracle) GEMM: plain, slow, obviously correct CPU code.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no source, header, table or helper
+ * with the GPU path.
+ *
+ * What it computes (paper section 3.1, "The baseline algorithm": the matrix
+ * multiplication C = C + A B with A m x k, B k x n, C m x n), generalised to
+ * the BLAS form C = alpha * op(A) * op(B) + beta * C0 with row-major storage:
+ *   op(A)(i,p) = A[i*lda + p]  if transA is 'N',  A[p*lda + i]  if 'T'
+ *   op(B)(p,j) = B[p*ldb + j]  if transB is 'N',  B[j*ldb + p]  if 'T'
+ * Each C(i,j) is the sum over p = 0..k-1, taken in increasing p, of
+ * op(A)(i,p) * op(B)(p,j): the paper's basic triple loop (section 5.1,
+ * "Basic GEMM with TVM") in the i -> p -> j nesting, with no blocking.
+ * Floating point is FP64; INT8 accumulates exactly in int64 and wraps the
+ * final value to int32 (two's complement).
+ *
+ * BLAS conventions (the paper defines only C += AB):
+ *   alpha == 0 or k == 0 : the product is not formed and A, B are not read;
+ *   beta  == 0           : C0 is not read (NaN/Inf in C0 do not propagate).
+ *
+ * Also here, each written from its format definition:
+ *   - bfloat16 round-to-nearest-even and the hi/mid/lo split of an FP32 value
+ *     into bf16 pieces (inputs of the split-product FP32-accurate path);
+ *   - exact decoders for bfloat16, IEEE binary16 and OCP FP8 E4M3FN codes.
+ */
+#include <stdint.h>
+#include <string.h>
+#include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define CHUNK 256
+
+static int is_t(char t) { return t == 'T' || t == 't' || t == 'C' || t == 'c'; }
+
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ---------------------------------------------------------------------- */
+/* FP64 GEMM.  C = alpha * op(A) op(B) + beta * C0.  C must not alias C0.   */
+/* Columns are visited in chunks of CHUNK so the row accumulator lives on   */
+/* the stack; each entry still sums p = 0..k-1 in order.                    */
+/* ---------------------------------------------------------------------- */
+void oracle_gemm_f64(char ta, char tb, int64_t m, int64_t n, int64_t k,
+                     double alpha, const double *A, int64_t lda,
+                     const double *B, int64_t ldb, double beta,
+                     const double *C0, int64_t ldc0, double *C, int64_t ldc)
+{
+    const int at = is_t(ta), bt = is_t(tb);
+    const int form = (alpha != 0.0) && (k > 0);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < m; ++i) {
+        double acc[CHUNK];
+        for (int64_t j0 = 0; j0 < n; j0 += CHUNK) {
+            const int64_t jn = (n - j0 < CHUNK) ? n - j0 : CHUNK;
+            for (int64_t j = 0; j < jn; ++j) acc[j] = 0.0;
+            if (form) {
+                for (int64_t p = 0; p < k; ++p) {
+                    const double a = at ? A[p * lda + i] : A[i * lda + p];
+                    for (int64_t j = 0; j < jn; ++j) {
+                        const double b = bt ? B[(j0 + j) * ldb + p] : B[p * ldb + (j0 + j)];
+                        acc[j] += a * b;
+                    }
+                }
+            }
+            for (int64_t j = 0; j < jn; ++j) {
+                double v = form ? alpha * acc[j] : 0.0;
+                if (beta != 0.0) v += beta * C0[i * ldc0 + (j0 + j)];
+                C[i * ldc + (j0 + j)] = v;
+            }
+        }
+    }
+}
+
+/* Selected entries of the same product: out[t] = C(rows[t], cols[t]). */
+void oracle_gemm_entries_f64(char ta, char tb, int64_t k, double alpha,
+                             const double *A, int64_t lda,
+                             const double *B, int64_t ldb, double beta,
+                             const double *C0, int64_t ldc0,
+                             int64_t count, const int64_t *rows,
+                             const int64_t *cols, double *out)
+{
+    const int at = is_t(ta), bt = is_t(tb);
+    const int form = (alpha != 0.0) && (k > 0);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < count; ++t) {
+        const int64_t i = rows[t], j = cols[t];
+        double s = 0.0;
+        if (form)
+            for (int64_t p = 0; p < k; ++p)
+                s += (at ? A[p * lda + i] : A[i * lda + p]) *
+                     (bt ? B[j * ldb + p] : B[p * ldb + j]);
+        double v = form ? alpha * s : 0.0;
+        if (beta != 0.0) v += beta * C0[i * ldc0 + j];
+        out[t] = v;
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Split-product form: op(A) = sum_u PA[u], op(B) = sum_v PB[v] (pieces     */
+/* stored with the same lda/ldb), and only the listed (u,v) piece products */
+/* are formed:  C = alpha * sum_p sum_t PA[u_t](i,p) PB[v_t](p,j) + beta*C0 */
+/* The inner sum over the listed pairs is taken for each p in list order.   */
+/* ---------------------------------------------------------------------- */
+void oracle_gemm_pieces_f64(char ta, char tb, int64_t m, int64_t n, int64_t k,
+                            double alpha, int npa, const double *const *PA, int64_t lda,
+                            int npb, const double *const *PB, int64_t ldb,
+                            int nterms, const int *tu, const int *tv,
+                            double beta, const double *C0, int64_t ldc0,
+                            double *C, int64_t ldc)
+{
+    const int at = is_t(ta), bt = is_t(tb);
+    const int form = (alpha != 0.0) && (k > 0);
+    (void)npa; (void)npb;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < m; ++i) {
+        double acc[CHUNK];
+        for (int64_t j0 = 0; j0 < n; j0 += CHUNK) {
+            const int64_t jn = (n - j0 < CHUNK) ? n - j0 : CHUNK;
+            for (int64_t j = 0; j < jn; ++j) acc[j] = 0.0;
+            if (form) {
+                for (int64_t p = 0; p < k; ++p) {
+                    for (int t = 0; t < nterms; ++t) {
+                        const double *Ap = PA[tu[t]], *Bp = PB[tv[t]];
+                        const double a = at ? Ap[p * lda + i] : Ap[i * lda + p];
+                        for (int64_t j = 0; j < jn; ++j) {
+                            const double b = bt ? Bp[(j0 + j) * ldb + p] : Bp[p * ldb + (j0 + j)];
+                            acc[j] += a * b;
+                        }
+                    }
+                }
+            }
+            for (int64_t j = 0; j < jn; ++j) {
+                double v = form ? alpha * acc[j] : 0.0;
+                if (beta != 0.0) v += beta * C0[i * ldc0 + (j0 + j)];
+                C[i * ldc + (j0 + j)] = v;
+            }
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* INT8 GEMM: exact int64 sums, then alpha*acc + beta*C0 in int64, wrapped  */
+/* to int32 by keeping the low 32 bits (two's complement).                  */
+/* ---------------------------------------------------------------------- */
+static int32_t wrap32(int64_t v)
+{
+    uint32_t u = (uint32_t)((uint64_t)v & 0xFFFFFFFFull);
+    int32_t r;
+    memcpy(&r, &u, sizeof r);
+    return r;
+}
+
+void oracle_gemm_i8(char ta, char tb, int64_t m, int64_t n, int64_t k,
+                    int64_t alpha, const int8_t *A, int64_t lda,
+                    const int8_t *B, int64_t ldb, int64_t beta,
+                    const int32_t *C0, int64_t ldc0, int32_t *C, int64_t ldc)
+{
+    const int at = is_t(ta), bt = is_t(tb);
+    const int form = (alpha != 0) && (k > 0);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t acc[CHUNK];
+        for (int64_t j0 = 0; j0 < n; j0 += CHUNK) {
+            const int64_t jn = (n - j0 < CHUNK) ? n - j0 : CHUNK;
+            for (int64_t j = 0; j < jn; ++j) acc[j] = 0;
+            if (form) {
+                for (int64_t p = 0; p < k; ++p) {
+                    const int64_t a = at ? A[p * lda + i] : A[i * lda + p];
+                    for (int64_t j = 0; j < jn; ++j) {
+                        const int64_t b = bt ? B[(j0 + j) * ldb + p] : B[p * ldb + (j0 + j)];
+                        acc[j] += a * b;
+                    }
+                }
+            }
+            for (int64_t j = 0; j < jn; ++j) {
+                /* unsigned arithmetic: the low 32 bits of the exact value */
+                uint64_t v = form ? (uint64_t)alpha * (uint64_t)acc[j] : 0u;
+                if (beta != 0) v += (uint64_t)beta * (uint64_t)(int64_t)C0[i * ldc0 + (j0 + j)];
+                C[i * ldc + (j0 + j)] = wrap32((int64_t)v);
+            }
+        }
+    }
+}
+
+void oracle_gemm_entries_i8(char ta, char tb, int64_t k, int64_t alpha,
+                            const int8_t *A, int64_t lda,
+                            const int8_t *B, int64_t ldb, int64_t beta,
+                            const int32_t *C0, int64_t ldc0,
+                            int64_t count, const int64_t *rows,
+                            const int64_t *cols, int32_t *out)
+{
+    const int at = is_t(ta), bt = is_t(tb);
+    const int form = (alpha != 0) && (k > 0);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < count; ++t) {
+        const int64_t i = rows[t], j = cols[t];
+        int64_t s = 0;
+        if (form)
+            for (int64_t p = 0; p < k; ++p)
+                s += (int64_t)(at ? A[p * lda + i] : A[i * lda + p]) *
+                     (int64_t)(bt ? B[j * ldb + p] : B[p * ldb + j]);
+        uint64_t v = form ? (uint64_t)alpha * (uint64_t)s : 0u;
+        if (beta != 0) v += (uint64_t)beta * (uint64_t)(int64_t)C0[i * ldc0 + j];
+        out[t] = wrap32((int64_t)v);
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Number formats.                                                          */
+/* ---------------------------------------------------------------------- */
+
+/* bfloat16 is the upper half of an IEEE binary32: decode by placing the 16 */
+/* bits in the high half of a 32-bit pattern.                               */
+void oracle_decode_bf16(const uint16_t *x, int64_t n, double *out)
+{
+    for (int64_t t = 0; t < n; ++t) {
+        uint32_t u = (uint32_t)x[t] << 16;
+        float f;
+        memcpy(&f, &u, sizeof f);
+        out[t] = (double)f;
+    }
+}
+
+/* IEEE binary16: 1 sign bit, 5 exponent bits (bias 15), 10 fraction bits. */
+void oracle_decode_f16(const uint16_t *x, int64_t n, double *out)
+{
+    for (int64_t t = 0; t < n; ++t) {
+        const uint16_t h = x[t];
+        const int s = h >> 15, e = (h >> 10) & 0x1F, f = h & 0x3FF;
+        double v;
+        if (e == 0)
+            v = ldexp((double)f, -24);             /* subnormal: f * 2^-14 * 2^-10 */
+        else if (e == 31)
+            v = f ? NAN : INFINITY;
+        else
+            v = ldexp(1.0 + (double)f / 1024.0, e - 15);
+        out[t] = s ? -v : v;
+    }
+}
+
+/* OCP 8-bit E4M3FN: 1 sign bit, 4 exponent bits (bias 7), 3 fraction bits.  */
+/* No infinities; exponent 15 with fraction 7 is NaN, so the largest finite */
+/* magnitude is 1.75 * 2^8 = 448.  Exponent 0 is subnormal: f * 2^-9.       */
+void oracle_decode_e4m3(const uint8_t *x, int64_t n, double *out)
+{
+    for (int64_t t = 0; t < n; ++t) {
+        const uint8_t b = x[t];
+        const int s = b >> 7, e = (b >> 3) & 0xF, f = b & 0x7;
+        double v;
+        if (e == 15 && f == 7)
+            v = NAN;
+        else if (e == 0)
+            v = ldexp((double)f, -9);
+        else
+            v = ldexp(1.0 + (double)f / 8.0, e - 7);
+        out[t] = s ? -v : v;
+    }
+}
+
+/* Round an FP32 value to bfloat16, round-to-nearest, ties to even, on the  */
+/* bit pattern: add 0x7FFF plus the lowest kept bit, then drop 16 bits.     */
+/* NaN stays a (quiet) NaN.  Overflow rounds to infinity as IEEE requires.   */
+static uint16_t rne_bf16(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, sizeof u);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu))
+        return (uint16_t)((u >> 16) | 0x0040u);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+static float bf16_to_f32(uint16_t h)
+{
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &u, sizeof f);
+    return f;
+}
+
+/* Split x into `pieces` bf16 values:  hi = RNE(x),  mid = RNE(x - hi),     */
+/* lo = RNE(x - hi - mid).  Each residual is formed in FP32, which is exact */
+/* here because it is a difference of nearby FP32 values.                   */
+void oracle_split_bf16(const float *x, int64_t n, int pieces, uint16_t *hi,
+                       uint16_t *mid, uint16_t *lo)
+{
+    for (int64_t t = 0; t < n; ++t) {
+        float r = x[t];
+        const uint16_t h = rne_bf16(r);
+        hi[t] = h;
+        if (pieces < 2) continue;
+        r = r - bf16_to_f32(h);
+        const uint16_t md = rne_bf16(r);
+        mid[t] = md;
+        if (pieces < 3) continue;
+        r = r - bf16_to_f32(md);
+        lo[t] = rne_bf16(r);
+    }
+}
