@@ -1,0 +1,220 @@
+"""Benchmark: the plain FP32 GEMM shape sweep on one MI355X.
+
+One step = one pass over the sweep (squares 1024..8192 and four ResNet50 v1.5
+im2col shapes at batch 16, each with beta = 0 and beta = 1), every GEMM a
+call of the C ABI on operands already resident in HBM.  Prints ONE JSON line
+with whole-job TFLOP/s, the roofline of the dominant kernel (the 8192^3
+GEMM; duration from HIP events on the launch stream), the oracle's CPU
+baseline on a bounded sample, and side measurements of the other paths
+(outside the timed region).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_PEAK_TFLOPS = 157.3      # MI355X dense FP32 (vector and MFMA)
+MFMA_PEAK = {"f32": 157.3, "bf16": 2516.6, "f16": 2516.6, "e4m3": 5033.0, "i8": 5033.0}
+HBM_PEAK_GBS = 8000.0
+
+SWEEP = [(1024, 1024, 1024), (2048, 2048, 2048), (4096, 4096, 4096), (8192, 8192, 8192),
+         (50176, 64, 576), (3136, 256, 2304), (196, 1024, 4608), (12544, 128, 1152)]
+BETAS = (0.0, 1.0)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-extras", action="store_true")
+    p.add_argument("--profile-only", action="store_true",
+                   help="only the timed steps (for rocprofv3 runs)")
+    return p.parse_args()
+
+
+def cpu_baseline(target_s=15.0):
+    """The oracle (FP64 triple loop) on a bounded sample of the sweep: for every
+    shape a band of rows of C (all columns, full k).  Returns TFLOP/s."""
+    import oracle
+    from paper_2310_20347_amd import inputs
+    # calibrate on a small band
+    m, n, k = 64, 1024, 1024
+    a = inputs.uniform((m, k), 1)
+    b = inputs.uniform((k, n), 2)
+    t0 = time.perf_counter()
+    oracle.gemm_f64("N", "N", m, n, k, 1.0, a, k, b, n)
+    rate = 2.0 * m * n * k / (time.perf_counter() - t0)
+    budget = target_s * rate / len(SWEEP)   # flops per shape
+    flops = 0.0
+    t = 0.0
+    rows_used = []
+    for i, (m, n, k) in enumerate(SWEEP):
+        rows = int(max(1, min(m, budget // (2.0 * n * k))))
+        a = inputs.uniform((rows, k), 100 + i)
+        b = inputs.uniform((k, n), 200 + i)
+        c0 = inputs.uniform((rows, n), 300 + i)
+        t0 = time.perf_counter()
+        oracle.gemm_f64("N", "N", rows, n, k, 1.0, a, k, b, n, 1.0, c0, n)
+        t += time.perf_counter() - t0
+        flops += 2.0 * rows * n * k
+        rows_used.append(rows)
+    return {"value": flops / t / 1e12, "unit": "TFLOP/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": ("FP64 oracle on a band of rows of C for each sweep shape (all columns, "
+                       f"full k; rows per shape {rows_used}), {flops / 1e9:.1f} GFLOP in "
+                       f"{t:.1f} s")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    import paper_2310_20347_amd as mg
+    from paper_2310_20347_amd import inputs
+
+    torch.cuda.set_device(0)
+    mg.gemm_init(None)
+    stream = torch.cuda.current_stream()
+
+    # operands, resident in HBM before timing
+    ops = []
+    for i, (m, n, k) in enumerate(SWEEP):
+        A = torch.from_numpy(inputs.uniform((m, k), inputs.seed_for(1, "A") + 10 * i)).cuda()
+        B = torch.from_numpy(inputs.uniform((k, n), inputs.seed_for(1, "B") + 10 * i)).cuda()
+        C0 = torch.from_numpy(inputs.uniform((m, n), inputs.seed_for(1, "C") + 10 * i)).cuda()
+        ops.append((m, n, k, A, B, C0, C0.clone()))
+    torch.cuda.synchronize()
+    flops_per_step = sum(2.0 * m * n * k for (m, n, k) in SWEEP) * len(BETAS)
+    dom = SWEEP.index((8192, 8192, 8192))
+    ev = []
+
+    def step(dtype, record):
+        for i, (m, n, k, A, B, C0, C) in enumerate(ops):
+            for beta in BETAS:
+                if record and i == dom:
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                mg.gemm("N", "N", m, n, k, 1.0, A, k, B, n, beta, C, n, dtype, stream=stream)
+                if record and i == dom:
+                    e1.record(stream)
+                    ev.append((e0, e1))
+
+    for _ in range(args.warmup):
+        step(mg.GEMM_F32, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(mg.GEMM_F32, True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = flops_per_step * args.steps / dt / 1e12
+    dom_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    m, n, k = SWEEP[dom]
+    achieved = 2.0 * m * n * k / (dom_ms * 1e-3) / 1e12
+    cfg = mg.config_info(mg.GEMM_F32, mg.last_config()["cfg"]) if mg.last_config()["cfg"] >= 0 else {}
+
+    out = {
+        "metric": "GEMM TFLOP/s and % MFMA peak vs plain FP32; grouped p50/p99 latency",
+        "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded U[-1,1] operands of the sweep shapes)",
+        "config": {"workload": "plain FP32 GEMM shape sweep: m=n=k in {1024,2048,4096,8192} and "
+                               "im2col shapes (50176,64,576) (3136,256,2304) (196,1024,4608) "
+                               "(12544,128,1152); beta in {0,1}; alpha=1; row-major NN",
+                   "gemms_per_step": len(SWEEP) * len(BETAS), "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "kernel": "gemm_tile_kernel FP32 8192^3",
+                     "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                     "avg_ms": round(dom_ms, 4), "tile": cfg},
+    }
+    if not args.profile_only and not args.no_extras:
+        out["paths"] = extras(mg, torch, stream, ops)
+    if not args.profile_only and not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+def _time_call(fn, torch, stream, reps=5):
+    fn()
+    torch.cuda.synchronize()
+    es = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        es.append((e0, e1))
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in es]))
+
+
+def extras(mg, torch, stream, ops):
+    """Other paths, timed outside the measured steps: the FP32-accurate split
+    product on the same sweep, and 8192^3 in every precision."""
+    from paper_2310_20347_amd import inputs
+    res = {}
+    tot_f32 = tot_x3 = 0.0
+    flops = 0.0
+    for (m, n, k, A, B, C0, C) in ops:
+        f32 = _time_call(lambda: mg.gemm("N", "N", m, n, k, 1.0, A, k, B, n, 0.0, C, n,
+                                         mg.GEMM_F32, stream=stream), torch, stream)
+        x3 = _time_call(lambda: mg.gemm("N", "N", m, n, k, 1.0, A, k, B, n, 0.0, C, n,
+                                        mg.GEMM_F32_BF16X3, stream=stream), torch, stream)
+        tot_f32 += f32
+        tot_x3 += x3
+        flops += 2.0 * m * n * k
+    res["sweep_beta0"] = {"f32_tflops": round(flops / tot_f32 / 1e9, 2),
+                          "bf16x3_tflops": round(flops / tot_x3 / 1e9, 2),
+                          "bf16x3_speedup_vs_f32": round(tot_f32 / tot_x3, 3)}
+    n = 8192
+    a32 = inputs.normal((n, n), inputs.seed_for(3, "A"))
+    b32 = inputs.normal((n, n), inputs.seed_for(3, "B"))
+    Cd = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    prec = {}
+    for name, dt, enc, peak, terms in (
+            ("f32", mg.GEMM_F32, None, 157.3, 1), ("bf16x3", mg.GEMM_F32_BF16X3_ONLY, None, 2516.6, 3),
+            ("bf16x6", mg.GEMM_F32_BF16X6, None, 2516.6, 6),
+            ("bf16", mg.GEMM_BF16, inputs.to_bf16_bits, 2516.6, 1),
+            ("f16", mg.GEMM_F16, inputs.to_f16_bits, 2516.6, 1),
+            ("e4m3", mg.GEMM_F8E4M3, inputs.to_e4m3_bits, 5033.0, 1)):
+        if enc is None:
+            Ad = torch.from_numpy(a32).cuda()
+            Bd = torch.from_numpy(b32).cuda()
+        else:
+            Ad = torch.from_numpy(enc(a32).view(np.int16) if enc is not inputs.to_e4m3_bits
+                                  else enc(a32)).cuda()
+            Bd = torch.from_numpy(enc(b32).view(np.int16) if enc is not inputs.to_e4m3_bits
+                                  else enc(b32)).cuda()
+        ms = _time_call(lambda: mg.gemm("N", "N", n, n, n, 1.0, Ad, n, Bd, n, 0.0, Cd, n, dt,
+                                        stream=stream), torch, stream)
+        tf = 2.0 * n ** 3 / ms / 1e9
+        prec[name] = {"ms": round(ms, 3), "tflops": round(tf, 1),
+                      "mfma_util": round(terms * tf / peak, 4)}
+        del Ad, Bd
+    ai = torch.from_numpy(inputs.int8_uniform((n, n), 41)).cuda()
+    bi = torch.from_numpy(inputs.int8_uniform((n, n), 42)).cuda()
+    Ci = torch.empty((n, n), dtype=torch.int32, device="cuda")
+    ms = _time_call(lambda: mg.gemm("N", "N", n, n, n, 1, ai, n, bi, n, 0, Ci, n, mg.GEMM_I8,
+                                    stream=stream), torch, stream)
+    prec["i8"] = {"ms": round(ms, 3), "tops": round(2.0 * n ** 3 / ms / 1e9, 1),
+                  "mfma_util": round(2.0 * n ** 3 / ms / 1e9 / 5033.0, 4)}
+    res["precision_8192"] = prec
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,210 @@
+/*
+ * mgemm: blocked GEMM family for AMD Instinct MI355X (gfx950) - C ABI.
+ *
+ * The operation is the paper's matrix multiplication C = C + A B
+ * (section 3.1, "The baseline algorithm"; A is m x k, B is k x n, C is
+ * m x n), generalised to the BLAS form
+ *
+ *     C = alpha * op(A) * op(B) + beta * C
+ *
+ * and computed with the five loops around a micro-kernel of section 3
+ * (Figures "Baseline (B3A2C0) and A3B2C0 algorithms" and "B3C2A0 and
+ * A3C2B0 algorithms"), panel packing (section 5.3) and a register-resident
+ * micro-tile (section 4.1), re-derived for CDNA4: packing is global->LDS
+ * staging, the micro-kernel is a tile of MFMA instructions.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Layout: ROW-MAJOR.  lda, ldb, ldc are row strides in elements.
+ *   transA 'N': A is stored m x k, lda >= max(1,k);  'T': stored k x m, lda >= max(1,m)
+ *   transB 'N': B is stored k x n, ldb >= max(1,n);  'T': stored n x k, ldb >= max(1,k)
+ *   ldc >= max(1,n).  Accepted trans characters: N n T t C c ('C' = 'T', real data).
+ * Types (by dtype):
+ *   GEMM_F32, GEMM_F32_BF16X3, GEMM_F32_BF16X3_ONLY, GEMM_F32_BF16X6:
+ *                       A, B float32;  C float32
+ *   GEMM_BF16:          A, B bfloat16 (raw 16-bit patterns); C float32
+ *   GEMM_F16:           A, B IEEE binary16;                   C float32
+ *   GEMM_F8E4M3:        A, B OCP FP8 E4M3FN bytes;            C float32
+ *   GEMM_I8:            A, B int8;                            C int32
+ *   Accumulation is FP32 for every float type and INT32 for GEMM_I8.
+ *   alpha and beta are passed as double and used as float32 by the float
+ *   paths; for GEMM_I8 they must be integers representable in int32 and the
+ *   epilogue wraps modulo 2^32 (two's complement).
+ * Pointers: A, B, C are DEVICE pointers owned by the caller, aligned at least
+ *   to their element size.  The library never frees or retains them.
+ * Semantics (BLAS):
+ *   m == 0 or n == 0                    -> returns 0, nothing is read or written
+ *   (alpha == 0 or k == 0), beta == 1   -> returns 0, nothing is read or written
+ *   alpha == 0 or k == 0                -> C = beta*C; A and B are not read
+ *   beta == 0                           -> C is not read (NaN/Inf in C are overwritten)
+ * Execution: asynchronous on the calling thread's current stream (see
+ *   gemm_set_stream); no host synchronisation.  Device faults surface at the
+ *   caller's next synchronisation.  Results are deterministic run to run: each
+ *   kernel configuration fixes its k-summation order.
+ * Errors: 0 on success; -i when the i-th argument (1-based, BLAS xerbla
+ *   convention) is invalid; a positive GEMM_E_* code otherwise.  No C++
+ *   exception crosses this interface.
+ * Threads: entry points may be called from several host threads; stream and
+ *   last-error state are per thread.
+ */
+#ifndef MGEMM_H
+#define MGEMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GEMM_F32 = 0,             /* plain FP32: FP32 MFMA (v_mfma_f32_16x16x4_f32)            */
+    GEMM_F32_BF16X3 = 1,      /* FP32-accurate: A, B split into bf16 pieces on the fly;    */
+                              /* 3 piece products when k >= 64, 6 when k < 64              */
+    GEMM_BF16 = 2,            /* bfloat16 inputs                                           */
+    GEMM_F16 = 3,             /* binary16 inputs                                           */
+    GEMM_F8E4M3 = 4,          /* OCP e4m3fn inputs, unit block scales                      */
+    GEMM_I8 = 5,              /* int8 inputs, int32 accumulate, bit-exact                  */
+    GEMM_F32_BF16X3_ONLY = 6, /* split product, always 3 terms (hi*hi, hi*mid, mid*hi)     */
+    GEMM_F32_BF16X6 = 7,      /* split product, always 6 terms (adds mid*mid, hi*lo, lo*hi)*/
+    GEMM_NUM_DTYPES = 8
+} gemm_dtype;
+
+enum {
+    GEMM_OK = 0,
+    GEMM_E_HIP = 1,          /* a HIP runtime call failed; see gemm_last_hip_error()      */
+    GEMM_E_UNSUPPORTED = 2,  /* no kernel built for this dtype / configuration             */
+    GEMM_E_NOINIT = 3,       /* no usable GPU device                                       */
+    GEMM_E_WORKSPACE = 4,    /* grouped problem count above the workspace capacity         */
+    GEMM_E_TUNE_TABLE = 5,   /* tuning table file unreadable or malformed                  */
+    GEMM_E_SERVE = 6         /* serving loop: invalid configuration or backend failure     */
+};
+
+/*
+ * gemm: C = alpha * op(A) * op(B) + beta * C on the current stream.
+ *   Arguments (1-based numbers used by the -i error convention):
+ *    1 transA, 2 transB, 3 m, 4 n, 5 k, 6 alpha, 7 A, 8 lda, 9 B, 10 ldb,
+ *   11 beta, 12 C, 13 ldc, 14 dtype.
+ *   Invalid: trans not in NnTtCc; m, n or k < 0; ld below the minimum above;
+ *   A or B NULL when they must be read; C NULL when it must be written;
+ *   dtype unknown; for GEMM_I8, alpha (-6) or beta (-11) not an int32 integer.
+ *   The loop order, the block sizes (mc, nc, kc) and the MFMA wave tile are
+ *   chosen per (dtype, trans, size bucket) from the tuning table (gemm_init).
+ */
+int gemm(char transA, char transB, int64_t m, int64_t n, int64_t k,
+         double alpha, const void *A, int64_t lda, const void *B, int64_t ldb,
+         double beta, void *C, int64_t ldc, int dtype);
+
+/* One problem of a grouped call; the fields mean what gemm()'s arguments do. */
+typedef struct {
+    char transA, transB;
+    int64_t m, n, k;
+    double alpha;
+    const void *A;
+    int64_t lda;
+    const void *B;
+    int64_t ldb;
+    double beta;
+    void *C;
+    int64_t ldc;
+} gemm_problem;
+
+/*
+ * gemm_grouped: `count` independent problems of one dtype in ONE persistent
+ * kernel launch (plus one host-to-device copy of the descriptor table) on the
+ * current stream.  `problems` is a HOST array, copied into library-owned
+ * pinned staging before return, so the caller may reuse it immediately.
+ * Each problem is validated as gemm() would: an invalid argument i of problem
+ * p returns -(1000*p + i) and nothing is launched.  Problems that gemm()
+ * would quick-return are skipped.  Output regions of different problems
+ * must not overlap.  Returns GEMM_E_WORKSPACE when count exceeds
+ * gemm_grouped_capacity().  The staging slot is reused after the stream has
+ * consumed it (an event guards reuse), so back-to-back calls are safe.
+ */
+int gemm_grouped(int64_t count, const gemm_problem *problems, int dtype);
+
+/* Maximum `count` accepted by gemm_grouped (fixed at initialisation). */
+int64_t gemm_grouped_capacity(void);
+
+/*
+ * Graph-capturable grouped launch.  gemm_grouped_capture_begin() returns (in
+ * *slot) a host pointer to a pinned descriptor slot owned by the library;
+ * the caller captures gemm_grouped_slot(slot, count, dtype) into a HIP graph
+ * on its stream, and before each replay may rewrite the problem list with
+ * gemm_grouped_slot_write(slot, count, problems, dtype) (which validates like
+ * gemm_grouped).  A replay re-reads the slot's pinned memory, so rewrite it
+ * only while no replay that uses it is in flight.
+ */
+int gemm_grouped_slot_create(void **slot);
+int gemm_grouped_slot_write(void *slot, int64_t count, const gemm_problem *problems,
+                            int dtype);
+int gemm_grouped_slot_launch(void *slot);
+void gemm_grouped_slot_destroy(void *slot);
+
+/*
+ * Stream for this host thread's subsequent calls: a hipStream_t, or NULL for
+ * the null stream.  The library does not take ownership.
+ */
+int gemm_set_stream(void *hip_stream);
+
+/*
+ * Initialise the library on the current device: query the device, register
+ * the compiled kernel family and load the tuning table from
+ * `tune_table_path` (JSON written by gemm_tune; NULL or "" = built-in
+ * defaults, or the path in the MGEMM_TUNE_TABLE environment variable).
+ * Optional: the first gemm call on a device initialises lazily with defaults,
+ * but that first call allocates, so call gemm_init before any graph capture.
+ */
+int gemm_init(const char *tune_table_path);
+void gemm_shutdown(void);
+
+/* Text of an error code (static storage). */
+const char *gemm_strerror(int code);
+
+/* The hipError_t behind the last GEMM_E_HIP on this thread. */
+int gemm_last_hip_error(void);
+
+/*
+ * Kernel family introspection (used by the tuner and the tests).
+ *   gemm_num_configs(dtype): number of compiled tile configurations.
+ *   gemm_config_info(dtype, id, out[8]): out = {mc, nc, kc, wave tile m,
+ *     wave tile n, threads, lds bytes, kind}; kind 0 = C resident in
+ *     registers, 1 = A resident, 2 = B resident (paper section 4).
+ *   gemm_force_config(dtype, id, order): pin the next calls on this thread
+ *     to configuration `id` with raster order `order` (0 = B3A2C0, column
+ *     panels outer; 1 = A3B2C0, row panels outer); id < 0 clears the pin.
+ *   gemm_last_config(out[3]): {dtype, id, order} used by this thread's last
+ *     gemm() launch, and the split-term count in out[3] (0 if not split).
+ */
+int gemm_num_configs(int dtype);
+int gemm_config_info(int dtype, int id, int64_t out[8]);
+int gemm_force_config(int dtype, int id, int order);
+int gemm_last_config(int64_t out[4]);
+
+/*
+ * Autotuner (paper section 8.4, "In search of the best micro-kernel": a
+ * search over micro-kernel shapes of a few dozen experiments).  For every
+ * (m, n, k) in `shapes` (3*count int64) it times each compiled configuration
+ * of `dtype` (both raster orders) on library-allocated scratch operands,
+ * keeps the fastest by median of `reps` launches, stores it under the
+ * shape's size bucket for trans ('N','N') and writes the table as JSON to
+ * `out_path` (NULL: keep in memory only).  Synchronous; allocates.
+ */
+int gemm_tune(int dtype, int64_t count, const int64_t *shapes, int reps,
+              const char *out_path);
+
+/*
+ * Fraction of a memory of `capacity_bytes` occupied by a rows x cols panel of
+ * `elem_bytes`-byte values: the occupancy measure of the paper's analytical
+ * cache model (section 8.4, Table 2: the L1 share of the micro-panel Br =
+ * kc x nr FP32 values in a 64 KiB L1).  The tuner uses it to prune
+ * configurations whose staged panels exceed a CU's LDS.  Returns -1 for
+ * negative sizes or non-positive element size / capacity.
+ */
+double gemm_panel_occupancy(int64_t rows, int64_t cols, int64_t elem_bytes,
+                            int64_t capacity_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGEMM_H */

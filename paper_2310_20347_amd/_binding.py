@@ -1,0 +1,248 @@
+"""ctypes binding of libmgemm.so: same names as the C ABI, marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Any, Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+GEMM_F32 = 0
+GEMM_F32_BF16X3 = 1
+GEMM_BF16 = 2
+GEMM_F16 = 3
+GEMM_F8E4M3 = 4
+GEMM_I8 = 5
+GEMM_F32_BF16X3_ONLY = 6
+GEMM_F32_BF16X6 = 7
+DTYPE_NAMES = {GEMM_F32: "f32", GEMM_F32_BF16X3: "bf16x3", GEMM_BF16: "bf16", GEMM_F16: "f16",
+               GEMM_F8E4M3: "e4m3", GEMM_I8: "i8", GEMM_F32_BF16X3_ONLY: "bf16x3_only",
+               GEMM_F32_BF16X6: "bf16x6"}
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+_C = ctypes.c_char
+_INT = ctypes.c_int
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("transA", _C), ("transB", _C), ("m", _I64), ("n", _I64), ("k", _I64),
+                ("alpha", _D), ("A", _P), ("lda", _I64), ("B", _P), ("ldb", _I64),
+                ("beta", _D), ("C", _P), ("ldc", _I64)]
+
+
+class MGemmError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where} failed with code {code}: {strerror(code)}")
+
+
+def lib_path() -> str:
+    return os.path.join(_HERE, "libmgemm.so")
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = lib_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run paper_2310_20347_amd/build.py "
+                           "(or __graft_entry__.build())")
+    L = ctypes.CDLL(path)
+    L.gemm.argtypes = [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64, _INT]
+    L.gemm.restype = _INT
+    L.gemm_grouped.argtypes = [_I64, ctypes.POINTER(_Problem), _INT]
+    L.gemm_grouped.restype = _INT
+    L.gemm_grouped_capacity.argtypes = []
+    L.gemm_grouped_capacity.restype = _I64
+    L.gemm_grouped_slot_create.argtypes = [ctypes.POINTER(_P)]
+    L.gemm_grouped_slot_create.restype = _INT
+    L.gemm_grouped_slot_write.argtypes = [_P, _I64, ctypes.POINTER(_Problem), _INT]
+    L.gemm_grouped_slot_write.restype = _INT
+    L.gemm_grouped_slot_launch.argtypes = [_P]
+    L.gemm_grouped_slot_launch.restype = _INT
+    L.gemm_grouped_slot_destroy.argtypes = [_P]
+    L.gemm_grouped_slot_destroy.restype = None
+    L.gemm_set_stream.argtypes = [_P]
+    L.gemm_set_stream.restype = _INT
+    L.gemm_init.argtypes = [ctypes.c_char_p]
+    L.gemm_init.restype = _INT
+    L.gemm_shutdown.argtypes = []
+    L.gemm_shutdown.restype = None
+    L.gemm_strerror.argtypes = [_INT]
+    L.gemm_strerror.restype = ctypes.c_char_p
+    L.gemm_last_hip_error.argtypes = []
+    L.gemm_last_hip_error.restype = _INT
+    L.gemm_num_configs.argtypes = [_INT]
+    L.gemm_num_configs.restype = _INT
+    L.gemm_config_info.argtypes = [_INT, _INT, ctypes.POINTER(_I64)]
+    L.gemm_config_info.restype = _INT
+    L.gemm_force_config.argtypes = [_INT, _INT, _INT]
+    L.gemm_force_config.restype = _INT
+    L.gemm_last_config.argtypes = [ctypes.POINTER(_I64)]
+    L.gemm_last_config.restype = _INT
+    L.gemm_tune.argtypes = [_INT, _I64, ctypes.POINTER(_I64), _INT, ctypes.c_char_p]
+    L.gemm_tune.restype = _INT
+    L.gemm_panel_occupancy.argtypes = [_I64, _I64, _I64, _I64]
+    L.gemm_panel_occupancy.restype = _D
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    return lib().gemm_strerror(int(code)).decode()
+
+
+def _check(rc: int, where: str) -> int:
+    if rc != 0:
+        raise MGemmError(rc, where)
+    return rc
+
+
+def _ptr(x: Any) -> Optional[int]:
+    """Device address of a torch tensor (or a raw int address)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        if hasattr(x, "is_cuda") and not x.is_cuda:
+            raise ValueError("gemm operands must be device tensors")
+        return x.data_ptr()
+    raise TypeError(f"cannot take the device address of {type(x)}")
+
+
+def set_stream(stream: Any = None) -> None:
+    """Stream for this thread's calls: a torch.cuda.Stream, a raw handle, or None
+    for torch's current stream."""
+    if stream is None:
+        import torch
+        handle = torch.cuda.current_stream().cuda_stream
+    elif isinstance(stream, int):
+        handle = stream
+    else:
+        handle = stream.cuda_stream
+    _check(lib().gemm_set_stream(handle or None), "gemm_set_stream")
+
+
+def _tc(t: str) -> bytes:
+    return t.encode() if isinstance(t, str) else bytes(t)
+
+
+def gemm(transA: str, transB: str, m: int, n: int, k: int, alpha: float, A, lda: int, B,
+         ldb: int, beta: float, C, ldc: int, dtype: int, stream: Any = None,
+         check: bool = True) -> int:
+    """C = alpha*op(A)*op(B) + beta*C on the current (or given) stream."""
+    set_stream(stream)
+    rc = lib().gemm(_tc(transA), _tc(transB), m, n, k, float(alpha), _ptr(A), lda, _ptr(B),
+                    ldb, float(beta), _ptr(C), ldc, int(dtype))
+    return _check(rc, "gemm") if check else rc
+
+
+@dataclass
+class Problem:
+    transA: str
+    transB: str
+    m: int
+    n: int
+    k: int
+    alpha: float
+    A: Any
+    lda: int
+    B: Any
+    ldb: int
+    beta: float
+    C: Any
+    ldc: int
+
+
+def _problems(problems: Sequence[Problem]):
+    arr = (_Problem * max(1, len(problems)))()
+    for i, p in enumerate(problems):
+        arr[i] = _Problem(_tc(p.transA), _tc(p.transB), p.m, p.n, p.k, float(p.alpha), _ptr(p.A),
+                          p.lda, _ptr(p.B), p.ldb, float(p.beta), _ptr(p.C), p.ldc)
+    return arr
+
+
+def gemm_grouped(problems: Sequence[Problem], dtype: int, stream: Any = None,
+                 check: bool = True) -> int:
+    """All problems in one persistent launch on the current (or given) stream."""
+    set_stream(stream)
+    arr = _problems(problems)
+    rc = lib().gemm_grouped(len(problems), arr, int(dtype))
+    return _check(rc, "gemm_grouped") if check else rc
+
+
+def gemm_grouped_capacity() -> int:
+    return int(lib().gemm_grouped_capacity())
+
+
+class GroupedSlot:
+    """A library-owned descriptor slot whose launch can be captured in a HIP graph."""
+
+    def __init__(self):
+        h = _P()
+        _check(lib().gemm_grouped_slot_create(ctypes.byref(h)), "gemm_grouped_slot_create")
+        self.handle = h
+
+    def write(self, problems: Sequence[Problem], dtype: int, check: bool = True) -> int:
+        rc = lib().gemm_grouped_slot_write(self.handle, len(problems), _problems(problems),
+                                           int(dtype))
+        return _check(rc, "gemm_grouped_slot_write") if check else rc
+
+    def launch(self, stream: Any = None) -> None:
+        set_stream(stream)
+        _check(lib().gemm_grouped_slot_launch(self.handle), "gemm_grouped_slot_launch")
+
+    def destroy(self) -> None:
+        if self.handle:
+            lib().gemm_grouped_slot_destroy(self.handle)
+            self.handle = None
+
+
+def gemm_init(tune_table_path: Optional[str] = None) -> None:
+    p = tune_table_path.encode() if tune_table_path else None
+    _check(lib().gemm_init(p), "gemm_init")
+
+
+def gemm_shutdown() -> None:
+    lib().gemm_shutdown()
+
+
+def num_configs(dtype: int) -> int:
+    return int(lib().gemm_num_configs(int(dtype)))
+
+
+def config_info(dtype: int, cfg: int) -> dict:
+    out = (_I64 * 8)()
+    _check(lib().gemm_config_info(int(dtype), int(cfg), out), "gemm_config_info")
+    keys = ("mc", "nc", "kc", "mr", "nr", "threads", "lds_bytes", "kind")
+    return dict(zip(keys, [int(v) for v in out]))
+
+
+def force_config(dtype: int, cfg: int, order: int = 0) -> None:
+    _check(lib().gemm_force_config(int(dtype), int(cfg), int(order)), "gemm_force_config")
+
+
+def last_config() -> dict:
+    out = (_I64 * 4)()
+    _check(lib().gemm_last_config(out), "gemm_last_config")
+    return {"dtype": int(out[0]), "cfg": int(out[1]), "order": int(out[2]), "terms": int(out[3])}
+
+
+def gemm_tune(dtype: int, shapes: Sequence[Sequence[int]], reps: int = 10,
+              out_path: Optional[str] = None) -> None:
+    flat = (_I64 * max(1, 3 * len(shapes)))(*[int(v) for s in shapes for v in s])
+    p = out_path.encode() if out_path else None
+    _check(lib().gemm_tune(int(dtype), len(shapes), flat, int(reps), p), "gemm_tune")
+
+
+def panel_occupancy(rows: int, cols: int, elem_bytes: int, capacity_bytes: int) -> float:
+    return float(lib().gemm_panel_occupancy(rows, cols, elem_bytes, capacity_bytes))

@@ -1,0 +1,512 @@
+// C ABI of the GEMM family: argument validation (BLAS conventions), quick
+// returns, configuration selection per size bucket, kernel launch on the
+// calling thread's stream, tuning table load/save, and introspection.
+#include <dlfcn.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "abi_internal.hpp"
+#include "mgemm.h"
+
+namespace mg {
+
+std::mutex g_mu;
+std::vector<KernelCfg> g_cfgs;
+std::vector<int> g_by_class[K_NUM];
+static bool g_registered = false;
+static bool g_table_loaded = false;
+DevState g_dev[kMaxDevices];
+std::map<TuneKey, TuneVal> g_table;
+thread_local Tls t_tls;
+
+Tls::Tls()
+{
+    for (int c = 0; c < K_NUM; ++c) {
+        force_id[c] = -1;
+        force_order[c] = 0;
+    }
+    for (int i = 0; i < 4; ++i) last[i] = -1;
+}
+
+int kclass_of(int dtype, int64_t k)
+{
+    switch (dtype) {
+    case GEMM_F32: return K_F32;
+    case GEMM_F32_BF16X3: return k >= 64 ? K_SPLIT2 : K_SPLIT3;
+    case GEMM_F32_BF16X3_ONLY: return K_SPLIT2;
+    case GEMM_F32_BF16X6: return K_SPLIT3;
+    case GEMM_BF16: return K_BF16;
+    case GEMM_F16: return K_F16;
+    case GEMM_F8E4M3: return K_F8;
+    case GEMM_I8: return K_I8;
+    default: return -1;
+    }
+}
+
+int elem_bytes(int kclass)
+{
+    switch (kclass) {
+    case K_F32: case K_SPLIT2: case K_SPLIT3: return 4;
+    case K_BF16: case K_F16: return 2;
+    default: return 1;
+    }
+}
+
+int split_terms(int kclass)
+{
+    return kclass == K_SPLIT2 ? 3 : kclass == K_SPLIT3 ? 6 : 0;
+}
+
+int bucket(int64_t x)
+{
+    int b = 0;
+    while (b < 62 && (int64_t(1) << (b + 1)) <= x) ++b;
+    return std::min(std::max(b, 4), 12);
+}
+
+static bool is_trans(char t) { return t == 'T' || t == 't' || t == 'C' || t == 'c'; }
+static bool trans_ok(char t) { return t == 'N' || t == 'n' || is_trans(t); }
+
+static bool int32_exact(double v)
+{
+    return std::isfinite(v) && v == std::floor(v) && v >= -2147483648.0 && v <= 2147483647.0;
+}
+
+int validate(char ta, char tb, int64_t m, int64_t n, int64_t k, double alpha, const void *A,
+             int64_t lda, const void *B, int64_t ldb, double beta, const void *C, int64_t ldc,
+             int dtype)
+{
+    if (!trans_ok(ta)) return -1;
+    if (!trans_ok(tb)) return -2;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (k < 0) return -5;
+    if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -14;
+    const bool is_int = dtype == GEMM_I8;
+    if (is_int && !int32_exact(alpha)) return -6;
+    const int es = elem_bytes(kclass_of(dtype, k));
+    const bool form = m > 0 && n > 0 && k > 0 && alpha != 0.0;
+    if (form && A == nullptr) return -7;
+    if (A != nullptr && (reinterpret_cast<uintptr_t>(A) % es) != 0) return -7;
+    if (lda < std::max<int64_t>(1, is_trans(ta) ? m : k)) return -8;
+    if (form && B == nullptr) return -9;
+    if (B != nullptr && (reinterpret_cast<uintptr_t>(B) % es) != 0) return -9;
+    if (ldb < std::max<int64_t>(1, is_trans(tb) ? k : n)) return -10;
+    if (is_int && !int32_exact(beta)) return -11;
+    const bool write = m > 0 && n > 0 && !((alpha == 0.0 || k == 0) && beta == 1.0);
+    if (write && C == nullptr) return -12;
+    if (C != nullptr && (reinterpret_cast<uintptr_t>(C) % 4) != 0) return -12;
+    if (ldc < std::max<int64_t>(1, n)) return -13;
+    return 0;
+}
+
+void ensure_registered()
+{
+    std::lock_guard<std::mutex> g(g_mu);
+    if (g_registered) return;
+    register_f32(g_cfgs);
+    register_split(g_cfgs);
+    register_half(g_cfgs);
+    register_byte(g_cfgs);
+    register_resident(g_cfgs);
+    for (size_t i = 0; i < g_cfgs.size(); ++i) g_by_class[g_cfgs[i].kclass].push_back((int)i);
+    g_registered = true;
+}
+
+// Directory of this shared library (for the tuning table shipped beside it).
+static std::string lib_dir()
+{
+    Dl_info info;
+    if (dladdr((void *)&lib_dir, &info) && info.dli_fname) {
+        std::string p(info.dli_fname);
+        size_t s = p.find_last_of('/');
+        if (s != std::string::npos) return p.substr(0, s);
+    }
+    return ".";
+}
+
+int device_state(DevState **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        t_tls.hip_err = (int)e;
+        return GEMM_E_NOINIT;
+    }
+    DevState &d = g_dev[dev];
+    if (!d.init) {
+        std::lock_guard<std::mutex> g(g_mu);
+        if (!d.init) {
+            int cus = 0;
+            e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            if (e != hipSuccess) {
+                t_tls.hip_err = (int)e;
+                return GEMM_E_HIP;
+            }
+            d.cus = cus;
+            d.device = dev;
+            d.init = true;
+        }
+    }
+    *out = &d;
+    return GEMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tuning table (JSON, one entry object per line).
+// ---------------------------------------------------------------------------
+static bool parse_entry(const std::string &obj, TuneKey &key, TuneVal &val)
+{
+    auto num = [&](const char *name, double &out) -> bool {
+        std::string pat = std::string("\"") + name + "\"";
+        size_t p = obj.find(pat);
+        if (p == std::string::npos) return false;
+        p = obj.find(':', p + pat.size());
+        if (p == std::string::npos) return false;
+        out = std::strtod(obj.c_str() + p + 1, nullptr);
+        return true;
+    };
+    double kc, tr, bm, bn, bk, cfg, order, group, us = 0;
+    if (!num("kclass", kc) || !num("trans", tr) || !num("bm", bm) || !num("bn", bn) ||
+        !num("bk", bk) || !num("cfg", cfg) || !num("order", order) || !num("group", group))
+        return false;
+    num("us", us);
+    key = TuneKey{(int)kc, (int)tr, (int)bm, (int)bn, (int)bk};
+    val = TuneVal{(int)cfg, (int)order, (int)group, us};
+    return key.kclass >= 0 && key.kclass < K_NUM && key.trans >= 0 && key.trans < 4;
+}
+
+int load_table(const char *path)
+{
+    std::ifstream f(path);
+    if (!f) return GEMM_E_TUNE_TABLE;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    size_t p = s.find("\"entries\"");
+    if (p == std::string::npos) return GEMM_E_TUNE_TABLE;
+    std::map<TuneKey, TuneVal> table;
+    while (true) {
+        size_t a = s.find('{', p);
+        if (a == std::string::npos) break;
+        size_t b = s.find('}', a);
+        if (b == std::string::npos) return GEMM_E_TUNE_TABLE;
+        TuneKey key;
+        TuneVal val;
+        if (!parse_entry(s.substr(a, b - a + 1), key, val)) return GEMM_E_TUNE_TABLE;
+        if (val.cfg < 0 || val.cfg >= (int)g_by_class[key.kclass].size() || val.group < 1 ||
+            val.order < 0 || val.order > 1)
+            return GEMM_E_TUNE_TABLE;
+        table[key] = val;
+        p = b + 1;
+    }
+    std::lock_guard<std::mutex> g(g_mu);
+    g_table = table;
+    return GEMM_OK;
+}
+
+int save_table(const char *path)
+{
+    std::lock_guard<std::mutex> g(g_mu);
+    std::ofstream f(path);
+    if (!f) return GEMM_E_TUNE_TABLE;
+    f << "{\"version\": 1, \"arch\": \"gfx950\", \"entries\": [\n";
+    size_t i = 0;
+    for (auto &kv : g_table) {
+        const TuneKey &k = kv.first;
+        const TuneVal &v = kv.second;
+        char line[256];
+        std::snprintf(line, sizeof line,
+                      " {\"kclass\": %d, \"trans\": %d, \"bm\": %d, \"bn\": %d, \"bk\": %d, "
+                      "\"cfg\": %d, \"order\": %d, \"group\": %d, \"us\": %.3f}%s\n",
+                      k.kclass, k.trans, k.bm, k.bn, k.bk, v.cfg, v.order, v.group, v.us,
+                      ++i < g_table.size() ? "," : "");
+        f << line;
+    }
+    f << "]}\n";
+    return f.good() ? GEMM_OK : GEMM_E_TUNE_TABLE;
+}
+
+static void ensure_table()
+{
+    if (g_table_loaded) return;
+    g_table_loaded = true;
+    const char *env = std::getenv("MGEMM_TUNE_TABLE");
+    if (env && *env) {
+        load_table(env);
+        return;
+    }
+    const std::string def = lib_dir() + "/mgemm_tune.json";
+    std::ifstream probe(def);
+    if (probe) load_table(def.c_str());
+}
+
+// Default choice without a table entry: the tile that minimises a crude
+// cost = waves of workgroups x per-tile work (mc*nc) + panel traffic (mc+nc).
+static void heuristic(int kclass, int64_t m, int64_t n, int cus, int &id, int &order, int &group)
+{
+    const std::vector<int> &ids = g_by_class[kclass];
+    double best = 1e300;
+    id = 0;
+    for (size_t i = 0; i < ids.size(); ++i) {
+        const KernelCfg &c = g_cfgs[ids[i]];
+        if (c.kind != 0) continue;
+        const double tiles = double((m + c.mc - 1) / c.mc) * double((n + c.nc - 1) / c.nc);
+        const double slots = double(cus) * std::max(1, (160 * 1024) / std::max(c.lds, 1));
+        const double waves = std::ceil(tiles / std::min(slots, double(cus) * 2));
+        const double cost = waves * (double(c.mc) * c.nc + 48.0 * (c.mc + c.nc));
+        if (cost < best * 0.999) {
+            best = cost;
+            id = (int)i;
+        }
+    }
+    order = 0;
+    group = 8;
+}
+
+void select_config(int kclass, int trans, int64_t m, int64_t n, int64_t k, int cus, int &id,
+                   int &order, int &group)
+{
+    if (t_tls.force_id[kclass] >= 0 && t_tls.force_id[kclass] < (int)g_by_class[kclass].size()) {
+        id = t_tls.force_id[kclass];
+        order = t_tls.force_order[kclass];
+        group = t_tls.force_group > 0 ? t_tls.force_group : 8;
+        return;
+    }
+    ensure_table();
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        auto it = g_table.find(TuneKey{kclass, trans, bucket(m), bucket(n), bucket(k)});
+        if (it != g_table.end()) {
+            id = it->second.cfg;
+            order = it->second.order;
+            group = it->second.group;
+            return;
+        }
+    }
+    heuristic(kclass, m, n, cus, id, order, group);
+}
+
+int launch_gemm(const KernelCfg &c, int trans, bool vec, const GemmArgs &a, hipStream_t s)
+{
+    const void *f = c.func[trans][vec ? 1 : 0];
+    if (!f) return GEMM_E_UNSUPPORTED;
+    const int64_t blocks = int64_t(a.tiles_m) * a.tiles_n;
+    if (blocks <= 0 || blocks > 0x7FFFFFFF) return GEMM_E_UNSUPPORTED;
+    GemmArgs copy = a;
+    void *args[] = {&copy};
+    hipError_t e = hipLaunchKernel(f, dim3((unsigned)blocks), dim3(c.threads), args, 0, s);
+    if (e != hipSuccess) {
+        t_tls.hip_err = (int)e;
+        return GEMM_E_HIP;
+    }
+    return GEMM_OK;
+}
+
+bool vec_ok(const void *X, int64_t ld, int es)
+{
+    return (reinterpret_cast<uintptr_t>(X) % 16) == 0 && ((ld * es) % 16) == 0;
+}
+
+// Fills kernel arguments and picks configuration + staging variant.
+// Returns the registry index, or -1 when nothing fits.
+int plan_gemm(int dtype, char ta, char tb, int64_t m, int64_t n, int64_t k, double alpha,
+              const void *A, int64_t lda, const void *B, int64_t ldb, double beta, void *C,
+              int64_t ldc, int cus, GemmArgs &a, int &trans, bool &vec, int &cfg_id, int &kclass)
+{
+    kclass = kclass_of(dtype, k);
+    trans = 2 * (is_trans(ta) ? 1 : 0) + (is_trans(tb) ? 1 : 0);
+    int order = 0, group = 8;
+    select_config(kclass, trans, m, n, k, cus, cfg_id, order, group);
+    const int es = elem_bytes(kclass);
+    vec = vec_ok(A, lda, es) && vec_ok(B, ldb, es);
+    int reg = g_by_class[kclass][cfg_id];
+    if (!g_cfgs[reg].func[trans][vec ? 1 : 0]) {
+        // the element-wise staging variant lives in the class's first configuration
+        cfg_id = 0;
+        reg = g_by_class[kclass][0];
+        if (!g_cfgs[reg].func[trans][vec ? 1 : 0]) return -1;
+    }
+    const KernelCfg &c = g_cfgs[reg];
+    a.A = A;
+    a.B = B;
+    a.C = C;
+    a.lda = lda;
+    a.ldb = ldb;
+    a.ldc = ldc;
+    a.m = (int)m;
+    a.n = (int)n;
+    a.k = (int)k;
+    a.alpha = (float)alpha;
+    a.beta = (float)beta;
+    a.ialpha = dtype == GEMM_I8 ? (int)alpha : 0;
+    a.ibeta = dtype == GEMM_I8 ? (int)beta : 0;
+    a.tiles_m = (int)((m + c.mc - 1) / c.mc);
+    a.tiles_n = (int)((n + c.nc - 1) / c.nc);
+    a.order = order;
+    a.group = std::max(1, group);
+    a.terms = split_terms(kclass);
+    return reg;
+}
+
+}  // namespace mg
+
+using namespace mg;
+
+extern "C" {
+
+int gemm(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha, const void *A,
+         int64_t lda, const void *B, int64_t ldb, double beta, void *C, int64_t ldc, int dtype)
+{
+    const int v = validate(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype);
+    if (v != 0) return v;
+    if (m == 0 || n == 0) return GEMM_OK;
+    if ((alpha == 0.0 || k == 0) && beta == 1.0) return GEMM_OK;
+    if (m > 0x7FFFFFFF || n > 0x7FFFFFFF || k > 0x7FFFFFFF) return GEMM_E_UNSUPPORTED;
+    ensure_registered();
+    DevState *d = nullptr;
+    int rc = device_state(&d);
+    if (rc != GEMM_OK) return rc;
+    hipStream_t s = t_tls.stream;
+    if (alpha == 0.0 || k == 0) {
+        launch_scale(C, ldc, (int)m, (int)n, beta, dtype == GEMM_I8, s);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            t_tls.hip_err = (int)e;
+            return GEMM_E_HIP;
+        }
+        t_tls.last[0] = dtype;
+        t_tls.last[1] = -1;
+        t_tls.last[2] = -1;
+        t_tls.last[3] = 0;
+        return GEMM_OK;
+    }
+    GemmArgs a;
+    int trans = 0, cfg = 0, kclass = 0;
+    bool vec = true;
+    const int reg = plan_gemm(dtype, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                              d->cus, a, trans, vec, cfg, kclass);
+    if (reg < 0) return GEMM_E_UNSUPPORTED;
+    rc = launch_gemm(g_cfgs[reg], trans, vec, a, s);
+    if (rc == GEMM_OK) {
+        t_tls.last[0] = dtype;
+        t_tls.last[1] = cfg;
+        t_tls.last[2] = a.order;
+        t_tls.last[3] = a.terms;
+    }
+    return rc;
+}
+
+int gemm_set_stream(void *hip_stream)
+{
+    t_tls.stream = (hipStream_t)hip_stream;
+    return GEMM_OK;
+}
+
+int gemm_init(const char *tune_table_path)
+{
+    ensure_registered();
+    DevState *d = nullptr;
+    int rc = device_state(&d);
+    if (rc != GEMM_OK) return rc;
+    if (tune_table_path && *tune_table_path) {
+        g_table_loaded = true;
+        return load_table(tune_table_path);
+    }
+    ensure_table();
+    return grouped_device_init(d);
+}
+
+void gemm_shutdown(void)
+{
+    for (int i = 0; i < kMaxDevices; ++i) grouped_device_free(&g_dev[i]);
+}
+
+const char *gemm_strerror(int code)
+{
+    if (code < 0) return "invalid argument (the code's magnitude is the argument number)";
+    switch (code) {
+    case GEMM_OK: return "success";
+    case GEMM_E_HIP: return "HIP runtime error";
+    case GEMM_E_UNSUPPORTED: return "unsupported dtype, size or configuration";
+    case GEMM_E_NOINIT: return "no usable GPU device";
+    case GEMM_E_WORKSPACE: return "grouped problem count exceeds workspace capacity";
+    case GEMM_E_TUNE_TABLE: return "tuning table unreadable or malformed";
+    case GEMM_E_SERVE: return "serving loop configuration or backend failure";
+    default: return "unknown error";
+    }
+}
+
+int gemm_last_hip_error(void) { return t_tls.hip_err; }
+
+static int class_for_query(int dtype)
+{
+    if (dtype == GEMM_F32_BF16X3) return K_SPLIT2;
+    return kclass_of(dtype, 0);
+}
+
+int gemm_num_configs(int dtype)
+{
+    if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -1;
+    ensure_registered();
+    return (int)g_by_class[class_for_query(dtype)].size();
+}
+
+int gemm_config_info(int dtype, int id, int64_t out[8])
+{
+    if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -1;
+    ensure_registered();
+    const std::vector<int> &ids = g_by_class[class_for_query(dtype)];
+    if (id < 0 || id >= (int)ids.size()) return -2;
+    if (!out) return -3;
+    const KernelCfg &c = g_cfgs[ids[id]];
+    out[0] = c.mc;
+    out[1] = c.nc;
+    out[2] = c.kc;
+    out[3] = c.mc / c.wm;
+    out[4] = c.nc / c.wn;
+    out[5] = c.threads;
+    out[6] = c.lds;
+    out[7] = c.kind;
+    return GEMM_OK;
+}
+
+int gemm_force_config(int dtype, int id, int order)
+{
+    if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -1;
+    if (order < 0 || order > 1) return -3;
+    ensure_registered();
+    int classes[2] = {class_for_query(dtype), -1};
+    if (dtype == GEMM_F32_BF16X3) classes[1] = K_SPLIT3;
+    for (int c : classes) {
+        if (c < 0) continue;
+        if (id >= (int)g_by_class[c].size()) {
+            if (dtype != GEMM_F32_BF16X3) return -2;
+            continue;
+        }
+        t_tls.force_id[c] = id < 0 ? -1 : id;
+        t_tls.force_order[c] = order;
+    }
+    return GEMM_OK;
+}
+
+int gemm_last_config(int64_t out[4])
+{
+    if (!out) return -1;
+    for (int i = 0; i < 4; ++i) out[i] = t_tls.last[i];
+    return GEMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// Shared host-side state and helpers of the C ABI (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "registry.hpp"
+
+namespace mg {
+
+constexpr int kMaxDevices = 64;
+
+// Per-device state: created on first use (or gemm_init) of a device.
+struct DevState {
+    bool init = false;
+    int device = 0;
+    int cus = 0;
+    // grouped launches: device descriptor tables and pinned host staging
+    bool grouped_ready = false;
+    void *grouped = nullptr;
+};
+
+// Tuning table key: kernel class, trans index (2*tA + tB), log2 size buckets.
+struct TuneKey {
+    int kclass, trans, bm, bn, bk;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(kclass, trans, bm, bn, bk) < std::tie(o.kclass, o.trans, o.bm, o.bn, o.bk);
+    }
+};
+struct TuneVal {
+    int cfg, order, group;
+    double us;
+};
+
+// Per-thread state.
+struct Tls {
+    hipStream_t stream = nullptr;
+    int force_id[K_NUM];
+    int force_order[K_NUM];
+    int force_group = 0;
+    int64_t last[4];
+    int hip_err = 0;
+    Tls();
+};
+
+extern std::mutex g_mu;
+extern std::vector<KernelCfg> g_cfgs;
+extern std::vector<int> g_by_class[K_NUM];
+extern DevState g_dev[kMaxDevices];
+extern std::map<TuneKey, TuneVal> g_table;
+extern thread_local Tls t_tls;
+
+int kclass_of(int dtype, int64_t k);
+int elem_bytes(int kclass);
+int split_terms(int kclass);
+int bucket(int64_t x);
+int validate(char ta, char tb, int64_t m, int64_t n, int64_t k, double alpha, const void *A,
+             int64_t lda, const void *B, int64_t ldb, double beta, const void *C, int64_t ldc,
+             int dtype);
+void ensure_registered();
+int device_state(DevState **out);
+int load_table(const char *path);
+int save_table(const char *path);
+void select_config(int kclass, int trans, int64_t m, int64_t n, int64_t k, int cus, int &id,
+                   int &order, int &group);
+bool vec_ok(const void *X, int64_t ld, int es);
+int plan_gemm(int dtype, char ta, char tb, int64_t m, int64_t n, int64_t k, double alpha,
+              const void *A, int64_t lda, const void *B, int64_t ldb, double beta, void *C,
+              int64_t ldc, int cus, GemmArgs &a, int &trans, bool &vec, int &cfg_id, int &kclass);
+int launch_gemm(const KernelCfg &c, int trans, bool vec, const GemmArgs &a, hipStream_t s);
+
+// grouped.hip
+int grouped_device_init(DevState *d);
+void grouped_device_free(DevState *d);
+
+}  // namespace mg

@@ -1,0 +1,46 @@
+// Registry of the compiled kernel family: one entry per (kernel dtype class,
+// tile configuration), each holding launchers for the four transposition
+// combinations and for the vectorised / element-wise staging variants.
+//
+// The family mirrors the paper's generator parameters (section 5,
+// "P0. Parameter list": m, n, k, mc, nc, kc, mr, nr, lanesize, dtype): here a
+// configuration fixes mc x nc (workgroup tile), the wave grid (hence the
+// micro-tile mr x nr), kc (one 128-byte LDS row per operand row) and the
+// number of LDS stages; the loop-order variant is a launch-time argument.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "device.hpp"
+
+namespace mg {
+
+// Kernel dtype classes (the ABI's split dtype maps to SPLIT2 or SPLIT3).
+enum KClass { K_F32 = 0, K_SPLIT2, K_SPLIT3, K_BF16, K_F16, K_F8, K_I8, K_NUM };
+
+struct KernelCfg {
+    int kclass = 0;
+    int mc = 0, nc = 0, kc = 0;
+    int wm = 0, wn = 0;     // waves along m and n
+    int threads = 0;
+    int lds = 0;            // bytes of LDS per workgroup
+    int stages = 0;
+    int kind = 0;           // 0: C resident (registers); 1: A resident; 2: B resident
+    // kernel entry per [trans index = 2*transA + transB][vectorised staging]
+    const void *func[4][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr},
+                              {nullptr, nullptr}};
+};
+
+// Each instantiation unit appends its configurations.
+void register_f32(std::vector<KernelCfg> &out);
+void register_split(std::vector<KernelCfg> &out);
+void register_half(std::vector<KernelCfg> &out);
+void register_byte(std::vector<KernelCfg> &out);
+void register_resident(std::vector<KernelCfg> &out);
+
+// Plain C = beta * C (alpha == 0 or k == 0), float or int32 elements.
+void launch_scale(void *C, int64_t ldc, int m, int n, double beta, bool is_int, hipStream_t s);
+
+}  // namespace mg

@@ -1,0 +1,468 @@
+// The C-resident tile kernel: loops L1..L5 of the paper's B3A2C0 / A3B2C0
+// algorithms (section 3.1, Figure "Baseline (B3A2C0) and A3B2C0 algorithms")
+// with packing (section 5.3) and a register-resident micro-tile (section 4.1),
+// mapped onto gfx950:
+//
+//   L1/L3 (jc, ic)  -> one workgroup per mc x nc tile of C; the raster order of
+//                      tile ids picks the variant (B3A2C0: consecutive
+//                      workgroups share a column panel of B; A3B2C0: a row
+//                      panel of A), with XCD-aware placement;
+//   L2 (pc)         -> the k loop over stages of kc values (not parallel);
+//   pack Ac, Bc     -> each stage's A and B panels are staged global -> LDS by
+//                      the whole workgroup, converted to the MFMA operand
+//                      format and laid out k-contiguous per row (the analogue
+//                      of the unit-stride micro-panels of the paper's packing
+//                      figure); loads for stage s+1 are in flight while stage s
+//                      is multiplied (the prefetch of section 6.2);
+//   L4/L5 (jr, ir)  -> waves: each owns an (mc/WM) x (nc/WN) micro-tile;
+//   L6 micro-kernel -> per kc stage, a chain of MFMA instructions over 16x16
+//                      accumulator blocks held in registers for the whole k
+//                      loop (section 4.1: rank-kf updates instead of rank-1).
+#pragma once
+
+#include "device.hpp"
+
+namespace mg {
+
+// ---------------------------------------------------------------------------
+// Tile raster: tile id -> (tile row, tile column) in the variant's loop order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void raster(int t, int tiles_m, int tiles_n, int order, int group,
+                                       int &tm, int &tn)
+{
+    if (order == 0) {  // B3A2C0: column panels (jc) outermost, in groups
+        const int per = group * tiles_m;
+        const int g = t / per, r = t - g * per;
+        const int width = min(group, tiles_n - g * group);
+        tn = g * group + r % width;
+        tm = r / width;
+    } else {           // A3B2C0: row panels (ic) outermost, in groups
+        const int per = group * tiles_n;
+        const int g = t / per, r = t - g * per;
+        const int height = min(group, tiles_m - g * group);
+        tm = g * group + r % height;
+        tn = r / height;
+    }
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b%8).
+// Renumber so that each XCD receives a contiguous range of tile ids, i.e.
+// neighbouring tiles (which share A/B panels) share one XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nblocks)
+{
+    const int xcd = b & 7, idx = b >> 3;
+    const int base = nblocks >> 3, rem = nblocks & 7;
+    return (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + idx;
+}
+
+// ---------------------------------------------------------------------------
+// Element-wise (masked) loads assembled into a 16-byte register vector.
+// ---------------------------------------------------------------------------
+template <int GES, int N>
+__device__ __forceinline__ u32x4 load_elems(const char *p, int valid)
+{
+    u32x4 v = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        if (e < valid) {
+            if constexpr (GES == 4) {
+                v[e] = ((const u32 *)p)[e];
+            } else if constexpr (GES == 2) {
+                v[e / 2] |= (u32)((const unsigned short *)p)[e] << (16 * (e % 2));
+            } else {
+                v[e / 4] |= (u32)((const unsigned char *)p)[e] << (8 * (e % 4));
+            }
+        }
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Staging of one operand panel (ROWS rows of m or n, KC values of k).
+//
+// KMODE (operand contiguous along k: A 'N', B 'T'): each item is one 16-byte
+// global vector along k, copied (or split) into its LDS row.
+// MN mode (operand contiguous along m/n: A 'T', B 'N'): each item is a block
+// of KV k-rows x MNV elements, loaded as KV vectors along m/n and transposed
+// in registers into MNV LDS chunks of 16 bytes along k.
+// ---------------------------------------------------------------------------
+template <class DT, int ROWS, int NT, bool KMODE, bool VEC>
+struct Stage {
+    static constexpr int KC = Kc<DT>::value;
+    static constexpr int GES = DT::GES;
+    // K mode
+    static constexpr int VK = 16 / GES;            // elements per 16 B global vector
+    static constexpr int VPR = KC / VK;            // vectors per panel row
+    static constexpr int NVEC = ROWS * VPR;
+    // MN mode
+    static constexpr int KV = 16 / DT::LES;        // k rows per block = one LDS chunk
+    static constexpr int MNV = DT::MNV;            // m/n elements per global vector
+    static constexpr int GVB = MNV * GES;          // bytes per global vector
+    static constexpr int MB = ROWS / MNV;
+    static constexpr int NBLK = (KC / KV) * MB;
+
+    static constexpr int ITEMS = KMODE ? NVEC : NBLK;
+    static constexpr int PER = (ITEMS + NT - 1) / NT;   // items per thread
+    static constexpr int DW = KMODE ? 4 : (KV * GVB) / 4;  // dwords per item
+    static_assert(ROWS % MNV == 0, "panel rows must be a multiple of the vector width");
+
+    u32 reg[PER][DW];
+
+    // Load stage starting at k0 from the operand X (row stride ld elements),
+    // whose panel starts at row0; R rows and K columns are valid.
+    __device__ __forceinline__ void load(const char *X, int64_t ld, int row0, int R, int k0,
+                                         int K, int tid)
+    {
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const int item = tid + it * NT;
+            if (ITEMS % NT != 0 && item >= ITEMS) break;
+            if constexpr (KMODE) {
+                const int row = item / VPR, kv = item % VPR;
+                const int grow = row0 + row, gk = k0 + kv * VK;
+                u32x4 v = {0u, 0u, 0u, 0u};
+                if (grow < R && gk < K) {
+                    const char *p = X + ((int64_t)grow * ld + gk) * GES;
+                    if (VEC && gk + VK <= K)
+                        v = *(const u32x4 *)p;
+                    else
+                        v = load_elems<GES, VK>(p, K - gk);
+                }
+#pragma unroll
+                for (int d = 0; d < 4; ++d) reg[it][d] = v[d];
+            } else {
+                const int mb = item % MB, kb = item / MB;
+                const int gmn = row0 + mb * MNV, gk0 = k0 + kb * KV;
+#pragma unroll
+                for (int r = 0; r < KV; ++r) {
+                    const int gk = gk0 + r;
+                    u32x4 v = {0u, 0u, 0u, 0u};
+                    if (gk < K && gmn < R) {
+                        const char *p = X + ((int64_t)gk * ld + gmn) * GES;
+                        if (VEC && gmn + MNV <= R) {
+                            if constexpr (GVB == 16) {
+                                v = *(const u32x4 *)p;
+                            } else {
+                                v[0] = *(const u32 *)p;
+                            }
+                        } else {
+                            v = load_elems<GES, MNV>(p, R - gmn);
+                        }
+                    }
+#pragma unroll
+                    for (int d = 0; d < GVB / 4; ++d) reg[it][r * (GVB / 4) + d] = v[d];
+                }
+            }
+        }
+    }
+
+    // Write the loaded stage into LDS: `planes` points at plane 0 of this
+    // operand's panel; consecutive planes are plane_bytes apart.
+    __device__ __forceinline__ void store(char *planes, int plane_bytes, int tid) const
+    {
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const int item = tid + it * NT;
+            if (ITEMS % NT != 0 && item >= ITEMS) break;
+            if constexpr (KMODE) {
+                const int row = item / VPR, kv = item % VPR;
+                if constexpr (!DT::SPLIT) {
+                    u32x4 v = {reg[it][0], reg[it][1], reg[it][2], reg[it][3]};
+                    *(u32x4 *)(planes + lds_off<MNV>(row, kv * 16)) = v;
+                } else {
+                    // 4 FP32 values -> 4 bf16 per plane (8 bytes per plane)
+                    u32 piece[DT::PLANES][4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        float x = __builtin_bit_cast(float, reg[it][e]);
+#pragma unroll
+                        for (int pl = 0; pl < DT::PLANES; ++pl) {
+                            const u32 h = bf16_bits(x);
+                            piece[pl][e] = h;
+                            x = x - bf16_val(h);
+                        }
+                    }
+#pragma unroll
+                    for (int pl = 0; pl < DT::PLANES; ++pl) {
+                        u32x2 w = {piece[pl][0] | (piece[pl][1] << 16),
+                                   piece[pl][2] | (piece[pl][3] << 16)};
+                        *(u32x2 *)(planes + pl * plane_bytes + lds_off<MNV>(row, kv * 8)) = w;
+                    }
+                }
+            } else {
+                const int mb = item % MB, kb = item / MB;
+#pragma unroll
+                for (int e = 0; e < MNV; ++e) {
+                    const int row = mb * MNV + e;
+                    if constexpr (DT::SPLIT) {
+                        // KV=8 k-rows of FP32 -> 8 bf16 per plane = one 16 B chunk
+                        u32 piece[DT::PLANES][8];
+#pragma unroll
+                        for (int r = 0; r < 8; ++r) {
+                            float x = __builtin_bit_cast(float, reg[it][r * 4 + e]);
+#pragma unroll
+                            for (int pl = 0; pl < DT::PLANES; ++pl) {
+                                const u32 h = bf16_bits(x);
+                                piece[pl][r] = h;
+                                x = x - bf16_val(h);
+                            }
+                        }
+#pragma unroll
+                        for (int pl = 0; pl < DT::PLANES; ++pl) {
+                            u32x4 w = {piece[pl][0] | (piece[pl][1] << 16),
+                                       piece[pl][2] | (piece[pl][3] << 16),
+                                       piece[pl][4] | (piece[pl][5] << 16),
+                                       piece[pl][6] | (piece[pl][7] << 16)};
+                            *(u32x4 *)(planes + pl * plane_bytes + lds_off<MNV>(row, kb * 16)) = w;
+                        }
+                    } else if constexpr (GES == 4) {
+                        // 4 k-rows x 4 floats: take element e of each row
+                        u32x4 w = {reg[it][0 * 4 + e], reg[it][1 * 4 + e], reg[it][2 * 4 + e],
+                                   reg[it][3 * 4 + e]};
+                        *(u32x4 *)(planes + lds_off<MNV>(row, kb * 16)) = w;
+                    } else if constexpr (GES == 2) {
+                        // 8 k-rows x 8 halves: half e of each row, paired into dwords
+                        const int d = e / 2, sh = 16 * (e % 2);
+                        u32 w4[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const u32 lo = (reg[it][(2 * q) * 4 + d] >> sh) & 0xFFFFu;
+                            const u32 hi = (reg[it][(2 * q + 1) * 4 + d] >> sh) & 0xFFFFu;
+                            w4[q] = lo | (hi << 16);
+                        }
+                        u32x4 w = {w4[0], w4[1], w4[2], w4[3]};
+                        *(u32x4 *)(planes + lds_off<MNV>(row, kb * 16)) = w;
+                    } else {
+                        // 16 k-rows x 4 bytes: byte e of each row, four per dword
+                        const int sh = 8 * e;
+                        u32 w4[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            w4[q] = ((reg[it][4 * q + 0] >> sh) & 0xFFu) |
+                                    (((reg[it][4 * q + 1] >> sh) & 0xFFu) << 8) |
+                                    (((reg[it][4 * q + 2] >> sh) & 0xFFu) << 16) |
+                                    (((reg[it][4 * q + 3] >> sh) & 0xFFu) << 24);
+                        }
+                        u32x4 w = {w4[0], w4[1], w4[2], w4[3]};
+                        *(u32x4 *)(planes + lds_off<MNV>(row, kb * 16)) = w;
+                    }
+                }
+            }
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// One fragment chunk of the micro-kernel: acc += a * b over KF values of k.
+// A lane of group g = lane/16 holds the k values g*KF/4 .. g*KF/4 + KF/4-1 of
+// its row (A) or column (B); A and B use the same k assignment, so every k of
+// the chunk is summed exactly once.
+// ---------------------------------------------------------------------------
+template <class DT>
+__device__ __forceinline__ void mma(typename AccOf<DT>::type &acc, const u32 (*a)[DT::FDW],
+                                    const u32 (*b)[DT::FDW])
+{
+    if constexpr (DT::SPLIT) {
+        // piece products, smallest first; planes: 0 = hi, 1 = mid, 2 = lo
+        constexpr int P = DT::PLANES;
+        constexpr int NT = (P == 2) ? 3 : 6;
+        constexpr int TU[6] = {P == 2 ? 1 : 2, P == 2 ? 0 : 0, P == 2 ? 0 : 1, 1, 0, 0};
+        constexpr int TV[6] = {P == 2 ? 0 : 0, P == 2 ? 1 : 2, P == 2 ? 0 : 1, 0, 1, 0};
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const u32 *x = a[TU[t]], *y = b[TV[t]];
+            u32x4 xv = {x[0], x[1], x[2], x[3]}, yv = {y[0], y[1], y[2], y[3]};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, xv),
+                                                          __builtin_bit_cast(bf16x8, yv), acc,
+                                                          0, 0, 0);
+        }
+    } else if constexpr (DT::GES == 4) {  // plain FP32: four k=4 MFMAs
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__builtin_bit_cast(float, a[0][s]),
+                                                      __builtin_bit_cast(float, b[0][s]), acc,
+                                                      0, 0, 0);
+    } else if constexpr (DT::GES == 2) {
+        u32x4 xv = {a[0][0], a[0][1], a[0][2], a[0][3]}, yv = {b[0][0], b[0][1], b[0][2], b[0][3]};
+        if constexpr (DT::HALF)
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, xv),
+                                                         __builtin_bit_cast(f16x8, yv), acc, 0,
+                                                         0, 0);
+        else
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, xv),
+                                                          __builtin_bit_cast(bf16x8, yv), acc,
+                                                          0, 0, 0);
+    } else if constexpr (DT::INT) {
+        i32x4 xv = {(int)a[0][0], (int)a[0][1], (int)a[0][2], (int)a[0][3]};
+        i32x4 yv = {(int)b[0][0], (int)b[0][1], (int)b[0][2], (int)b[0][3]};
+        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(xv, yv, acc, 0, 0, 0);
+    } else {  // FP8 e4m3 (format code 0 for both operands), unit E8M0 scales (127)
+        i32x8 xv, yv;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            xv[d] = (int)a[0][d];
+            yv[d] = (int)b[0][d];
+        }
+        acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(xv, yv, acc, 0, 0, 0, 127, 0, 127);
+    }
+}
+
+// Read one MFMA operand fragment (all planes) of the 16-row block at `row`.
+template <class DT>
+__device__ __forceinline__ void read_frag(const char *planes, int plane_bytes, int row, int chunk,
+                                          int lane, u32 (*f)[DT::FDW])
+{
+    const int r = row + (lane & 15);
+    const int byte = chunk * (DT::KF * DT::LES) + (lane >> 4) * (DT::FDW * 4);
+#pragma unroll
+    for (int pl = 0; pl < DT::PLANES; ++pl) {
+#pragma unroll
+        for (int h = 0; h < DT::FDW / 4; ++h) {
+            const u32x4 v =
+                *(const u32x4 *)(planes + pl * plane_bytes + lds_off<DT::MNV>(r, byte + 16 * h));
+#pragma unroll
+            for (int d = 0; d < 4; ++d) f[pl][4 * h + d] = v[d];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The tile: C[m0:m0+MC, n0:n0+NC] = alpha * op(A) op(B) + beta * C.
+// ---------------------------------------------------------------------------
+template <class DT, int MC, int NC, int WM, int WN, bool TA, bool TB, bool VEC, int STAGES>
+struct Tile {
+    static constexpr int NT = 64 * WM * WN;
+    static constexpr int KC = Kc<DT>::value;
+    static constexpr int WTM = MC / WM, WTN = NC / WN;   // wave micro-tile (mr x nr)
+    static constexpr int FM = WTM / 16, FN = WTN / 16;   // 16x16 MFMA blocks per wave
+    static constexpr int PLANE_A = MC * 128, PLANE_B = NC * 128;
+    static constexpr int STAGE_BYTES = DT::PLANES * (PLANE_A + PLANE_B);
+    static constexpr int LDS_BYTES = STAGES * STAGE_BYTES;
+    static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile must be whole MFMA blocks");
+    static_assert(STAGES == 1 || STAGES == 2, "one or two LDS stages");
+    static_assert(LDS_BYTES <= 160 * 1024, "LDS budget of one CU");
+    typedef typename AccOf<DT>::type Acc;
+    typedef Stage<DT, MC, NT, !TA, VEC> StageA;   // A 'N' is contiguous along k
+    typedef Stage<DT, NC, NT, TB, VEC> StageB;    // B 'T' is contiguous along k
+
+    static __device__ __forceinline__ void compute(const char *buf, Acc (*acc)[FN], int wm,
+                                                   int wn, int lane)
+    {
+        const char *pa = buf;
+        const char *pb = buf + DT::PLANES * PLANE_A;
+#pragma unroll
+        for (int c = 0; c < KC / DT::KF; ++c) {
+            u32 fa[FM][DT::PLANES][DT::FDW];
+            u32 fb[FN][DT::PLANES][DT::FDW];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                read_frag<DT>(pa, PLANE_A, wm * WTM + 16 * i, c, lane, fa[i]);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                read_frag<DT>(pb, PLANE_B, wn * WTN + 16 * j, c, lane, fb[j]);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) mma<DT>(acc[i][j], fa[i], fb[j]);
+        }
+    }
+
+    // Computes tile (tm, tn) of problem p using `lds` (LDS_BYTES bytes).
+    static __device__ __forceinline__ void run(const GemmArgs &p, int tm, int tn, char *lds)
+    {
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const int wm = wave % WM, wn = wave / WM;
+        const int m0 = tm * MC, n0 = tn * NC;
+
+        Acc acc[FM][FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+
+        const bool form = p.k > 0 && (DT::INT ? p.ialpha != 0 : p.alpha != 0.0f);
+        const int nk = form ? (p.k + KC - 1) / KC : 0;
+        const char *A = (const char *)p.A;
+        const char *B = (const char *)p.B;
+
+        StageA sa;
+        StageB sb;
+        if (nk > 0) {
+            sa.load(A, p.lda, m0, p.m, 0, p.k, tid);
+            sb.load(B, p.ldb, n0, p.n, 0, p.k, tid);
+        }
+        if constexpr (STAGES == 2) {
+            if (nk > 0) {
+                sa.store(lds, PLANE_A, tid);
+                sb.store(lds + DT::PLANES * PLANE_A, PLANE_B, tid);
+            }
+            __syncthreads();
+            for (int s = 0; s < nk; ++s) {
+                char *cur = lds + (s & 1) * STAGE_BYTES;
+                char *nxt = lds + ((s + 1) & 1) * STAGE_BYTES;
+                if (s + 1 < nk) {
+                    sa.load(A, p.lda, m0, p.m, (s + 1) * KC, p.k, tid);
+                    sb.load(B, p.ldb, n0, p.n, (s + 1) * KC, p.k, tid);
+                }
+                compute(cur, acc, wm, wn, lane);
+                if (s + 1 < nk) {
+                    sa.store(nxt, PLANE_A, tid);
+                    sb.store(nxt + DT::PLANES * PLANE_A, PLANE_B, tid);
+                }
+                __syncthreads();
+            }
+        } else {
+            for (int s = 0; s < nk; ++s) {
+                sa.store(lds, PLANE_A, tid);
+                sb.store(lds + DT::PLANES * PLANE_A, PLANE_B, tid);
+                __syncthreads();
+                if (s + 1 < nk) {
+                    sa.load(A, p.lda, m0, p.m, (s + 1) * KC, p.k, tid);
+                    sb.load(B, p.ldb, n0, p.n, (s + 1) * KC, p.k, tid);
+                }
+                compute(lds, acc, wm, wn, lane);
+                __syncthreads();
+            }
+        }
+
+        // Epilogue: C = alpha * acc + beta * C (C not read when beta == 0).
+        // Accumulator block layout: lane l, register r -> row 4*(l/16)+r, col l%16.
+        const int rbase = m0 + wm * WTM + 4 * (lane >> 4);
+        const int cbase = n0 + wn * WTN + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = rbase + 16 * i + r, col = cbase + 16 * j;
+                    if (row < p.m && col < p.n) {
+                        if constexpr (DT::INT) {
+                            int *c = (int *)p.C + (int64_t)row * p.ldc + col;
+                            u32 v = (u32)p.ialpha * (u32)acc[i][j][r];
+                            if (p.ibeta != 0) v += (u32)p.ibeta * (u32)(*c);
+                            *c = (int)v;
+                        } else {
+                            float *c = (float *)p.C + (int64_t)row * p.ldc + col;
+                            float v = p.alpha * acc[i][j][r];
+                            if (p.beta != 0.0f) v = __builtin_fmaf(p.beta, *c, v);
+                            *c = v;
+                        }
+                    }
+                }
+    }
+};
+
+// One workgroup per tile.
+template <class T>
+__global__ void __launch_bounds__(T::NT) gemm_tile_kernel(GemmArgs p)
+{
+    __shared__ __attribute__((aligned(16))) char lds[T::LDS_BYTES];
+    const int nblocks = p.tiles_m * p.tiles_n;
+    const int t = xcd_remap(blockIdx.x, nblocks);
+    int tm, tn;
+    raster(t, p.tiles_m, p.tiles_n, p.order, p.group, tm, tn);
+    T::run(p, tm, tn, lds);
+}
+
+}  // namespace mg

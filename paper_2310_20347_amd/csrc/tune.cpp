@@ -1,0 +1,153 @@
+// Autotuner: the paper's search over micro-kernel shapes (section 8.4, "In
+// search of the best micro-kernel": a two-dimensional (mr, nr) space that
+// takes a few dozen experiments and can be automated), here over the
+// compiled tile configurations x raster order (B3A2C0 / A3B2C0) x raster
+// group, with analytical pruning (the role the paper gives to the cache
+// model of section 8.2): configurations whose kernels use scratch (spills;
+// section 8.7 shows a spilling micro-kernel losing half its speed) are
+// rejected, and so are configurations whose staged panels do not fit LDS.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <vector>
+
+#include "abi_internal.hpp"
+#include "mgemm.h"
+
+namespace mg {
+void launch_fill(void *p, int64_t count, int kind, uint32_t seed, hipStream_t s);
+}
+
+using namespace mg;
+
+static int fill_kind(int kclass)
+{
+    switch (kclass) {
+    case K_F32: case K_SPLIT2: case K_SPLIT3: return 0;
+    case K_BF16: return 1;
+    case K_F16: return 2;
+    case K_F8: return 3;
+    default: return 4;
+    }
+}
+
+extern "C" double gemm_panel_occupancy(int64_t rows, int64_t cols, int64_t elem_bytes,
+                                       int64_t capacity_bytes)
+{
+    if (rows < 0 || cols < 0 || elem_bytes <= 0 || capacity_bytes <= 0) return -1.0;
+    return double(rows) * double(cols) * double(elem_bytes) / double(capacity_bytes);
+}
+
+extern "C" int gemm_tune(int dtype, int64_t count, const int64_t *shapes, int reps,
+                         const char *out_path)
+{
+    if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -1;
+    if (count < 0) return -2;
+    if (count > 0 && !shapes) return -3;
+    if (reps < 1) return -4;
+    ensure_registered();
+    DevState *d = nullptr;
+    int rc = device_state(&d);
+    if (rc != GEMM_OK) return rc;
+
+    // scratch operands sized for the largest shape
+    size_t maxA = 0, maxB = 0, maxC = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        const int64_t m = shapes[3 * i], n = shapes[3 * i + 1], k = shapes[3 * i + 2];
+        if (m <= 0 || n <= 0 || k <= 0 || m > 0x7FFFFFFF || n > 0x7FFFFFFF || k > 0x7FFFFFFF)
+            return -3;
+        const int es = elem_bytes(kclass_of(dtype, k));
+        maxA = std::max(maxA, size_t(m * k * es));
+        maxB = std::max(maxB, size_t(k * n * es));
+        maxC = std::max(maxC, size_t(m * n * 4));
+    }
+    void *A = nullptr, *B = nullptr, *C = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto fail = [&](hipError_t e) {
+        t_tls.hip_err = (int)e;
+        if (A) (void)hipFree(A);
+        if (B) (void)hipFree(B);
+        if (C) (void)hipFree(C);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (s) (void)hipStreamDestroy(s);
+        return GEMM_E_HIP;
+    };
+    hipError_t e;
+    if ((e = hipMalloc(&A, std::max<size_t>(maxA, 16))) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&B, std::max<size_t>(maxB, 16))) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&C, std::max<size_t>(maxC, 16))) != hipSuccess) return fail(e);
+    if ((e = hipStreamCreate(&s)) != hipSuccess) return fail(e);
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return fail(e);
+    if ((e = hipEventCreate(&e1)) != hipSuccess) return fail(e);
+
+    static const int kGroups[3] = {4, 8, 16};
+    for (int64_t i = 0; i < count; ++i) {
+        const int64_t m = shapes[3 * i], n = shapes[3 * i + 1], k = shapes[3 * i + 2];
+        const int kclass = kclass_of(dtype, k);
+        launch_fill(A, m * k, fill_kind(kclass), 1u, s);
+        launch_fill(B, k * n, fill_kind(kclass), 2u, s);
+        double best_us = 1e300;
+        TuneVal best{0, 0, 8, 0.0};
+        const std::vector<int> &ids = g_by_class[kclass];
+        for (size_t id = 0; id < ids.size(); ++id) {
+            const KernelCfg &c = g_cfgs[ids[id]];
+            if (!c.func[0][1]) continue;
+            hipFuncAttributes attr;
+            if (hipFuncGetAttributes(&attr, c.func[0][1]) == hipSuccess && attr.localSizeBytes > 0)
+                continue;   // spills: rejected
+            if (gemm_panel_occupancy(1, c.lds, 1, 160 * 1024) > 1.0)
+                continue;   // staged panels exceed one CU's LDS
+            for (int order = 0; order < 2; ++order) {
+                for (int gi = 0; gi < 3; ++gi) {
+                    GemmArgs a;
+                    int trans = 0, cfg = 0, kc2 = 0;
+                    bool vec = true;
+                    const int saved = t_tls.force_id[kclass];
+                    const int saved_o = t_tls.force_order[kclass];
+                    t_tls.force_id[kclass] = (int)id;
+                    t_tls.force_order[kclass] = order;
+                    t_tls.force_group = kGroups[gi];
+                    const int reg = plan_gemm(dtype, 'N', 'N', m, n, k, 1.0, A, k, B, n, 0.0, C, n,
+                                              d->cus, a, trans, vec, cfg, kc2);
+                    t_tls.force_id[kclass] = saved;
+                    t_tls.force_order[kclass] = saved_o;
+                    t_tls.force_group = 0;
+                    if (reg < 0 || cfg != (int)id) continue;
+                    std::vector<float> ms;
+                    for (int r = 0; r < reps + 2; ++r) {
+                        (void)hipEventRecord(e0, s);
+                        if (launch_gemm(g_cfgs[reg], trans, vec, a, s) != GEMM_OK) break;
+                        (void)hipEventRecord(e1, s);
+                        if ((e = hipEventSynchronize(e1)) != hipSuccess) return fail(e);
+                        float t = 0;
+                        (void)hipEventElapsedTime(&t, e0, e1);
+                        if (r >= 2) ms.push_back(t);
+                    }
+                    if ((int)ms.size() != reps) continue;
+                    std::sort(ms.begin(), ms.end());
+                    const double us = 1e3 * ms[ms.size() / 2];
+                    if (us < best_us) {
+                        best_us = us;
+                        best = TuneVal{(int)id, order, kGroups[gi], us};
+                    }
+                    if (c.kind != 0) break;   // raster group is irrelevant to these
+                }
+            }
+        }
+        if (best_us < 1e300) {
+            std::lock_guard<std::mutex> g(g_mu);
+            g_table[TuneKey{kclass, 0, bucket(m), bucket(n), bucket(k)}] = best;
+        }
+    }
+    (void)hipFree(A);
+    (void)hipFree(B);
+    (void)hipFree(C);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(s);
+    if (out_path && *out_path) return save_table(out_path);
+    return GEMM_OK;
+}

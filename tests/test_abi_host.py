@@ -1,0 +1,109 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function the public headers declare, validates arguments with the BLAS
+-i convention before touching a device, and quick-returns where BLAS does."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+import paper_2310_20347_amd as mg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        for m in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, re.M):
+            if m.group(1) not in ("if", "while", "for", "return", "sizeof"):
+                names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert {"gemm", "gemm_grouped", "gemm_init", "gemm_tune"} <= names
+    lib = ctypes.CDLL(mg.lib_path())
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, f"declared but not exported: {missing}"
+
+
+def call(ta="N", tb="N", m=4, n=5, k=3, alpha=1.0, A=0x1000, lda=3, B=0x2000, ldb=5, beta=0.0,
+         C=0x3000, ldc=5, dtype=mg.GEMM_F32):
+    return mg.lib().gemm(ta.encode(), tb.encode(), m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                         dtype)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(ta="X"), -1), (dict(tb="q"), -2), (dict(m=-1), -3), (dict(n=-1), -4), (dict(k=-1), -5),
+    (dict(A=None), -7), (dict(A=0x1001), -7), (dict(lda=2), -8), (dict(ta="T", lda=3), -8),
+    (dict(B=None), -9), (dict(ldb=4), -10), (dict(tb="T", ldb=2), -10), (dict(C=None), -12),
+    (dict(ldc=4), -13), (dict(dtype=99), -14), (dict(dtype=-1), -14),
+    (dict(dtype=mg.GEMM_I8, alpha=0.5), -6), (dict(dtype=mg.GEMM_I8, beta=2.5), -11),
+    (dict(dtype=mg.GEMM_I8, alpha=2.0 ** 31), -6),
+])
+def test_invalid_arguments_report_their_position(kw, code):
+    assert call(**kw) == code
+
+
+def test_first_invalid_argument_wins():
+    assert call(ta="X", m=-1, ldc=0) == -1
+    assert call(m=-1, ldc=0) == -3
+
+
+def test_transposed_leading_dimensions():
+    # 'T' A is stored k x m: lda >= m; 'T' B stored n x k: ldb >= k
+    assert call(ta="T", lda=4, ldc=0) == -13       # lda ok, fails later at ldc
+    assert call(tb="T", ldb=3, ldc=0) == -13
+    assert call(ta="t", tb="c", lda=4, ldb=3, ldc=0) == -13   # lower case and 'C' accepted
+
+
+def test_quick_returns_touch_nothing():
+    # no device is needed: nothing is launched
+    assert call(m=0, A=None, B=None, C=None) == 0
+    assert call(n=0, A=None, B=None, C=None) == 0
+    assert call(k=0, beta=1.0, A=None, B=None, C=None, lda=1) == 0
+    assert call(alpha=0.0, beta=1.0, A=None, B=None, C=None) == 0
+
+
+def test_null_operands_allowed_when_not_read():
+    # alpha == 0: A, B not read; the call proceeds to the device (which may be absent)
+    rc = call(alpha=0.0, beta=2.0, A=None, B=None)
+    assert rc in (0, 3)
+
+
+def test_strerror_and_config_introspection():
+    assert "invalid" in mg.strerror(-3)
+    assert mg.strerror(0) == "success"
+    for dt in range(8):
+        n = mg.num_configs(dt)
+        assert n >= 2
+        for c in range(n):
+            info = mg.config_info(dt, c)
+            assert info["mc"] % info["mr"] == 0 and info["nc"] % info["nr"] == 0
+            assert info["lds_bytes"] <= 160 * 1024
+            assert info["kc"] * {0: 4, 1: 2, 2: 2, 3: 2, 4: 1, 5: 1, 6: 2, 7: 2}[dt] == 128
+
+
+def test_panel_occupancy_reproduces_paper_table2():
+    rows = [list(map(float, ln.split())) for ln in open(os.path.join(GOLDEN, "table2_l1_occupancy.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 14
+    for layer, kc, nr, pct in rows:
+        got = 100.0 * mg.panel_occupancy(int(kc), int(nr), 4, 64 * 1024)
+        # the table prints 3 significant figures (e.g. 18.75 -> 18.80)
+        assert float(f"{got:.3g}") == pct, (layer, kc, nr, got, pct)
+    assert mg.panel_occupancy(-1, 1, 4, 10) == -1.0
+
+
+def test_no_device_reports_noinit():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert call() == 3

@@ -1,0 +1,179 @@
+"""GPU parity of the single-GEMM path (through the C ABI) against the oracle.
+
+Bars: INT8 bit-exact; every float path within 2e-6 (normalised) of the oracle
+run on the inputs the kernel multiplies; FP32 and the split path within 2e-6
+and BF16/FP16 within 8e-3 of the oracle on the FP32 source; small-integer
+data bit-exact on every path.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2310_20347_amd as mg
+from paper_2310_20347_amd import inputs
+
+from gemm_cases import ALL_DTYPES, Case, check, run_case, to_device
+
+pytestmark = pytest.mark.gpu
+
+TRANS = [("N", "N"), ("N", "T"), ("T", "N"), ("T", "T")]
+SHAPES = [(257, 191, 203), (1, 1, 1), (17, 15, 255), (130, 300, 517), (64, 128, 16)]
+
+
+def _ab(dtype):
+    return (3.0, -2.0) if dtype == mg.GEMM_I8 else (1.5, -0.5)
+
+
+@pytest.mark.parametrize("dtype", ALL_DTYPES, ids=lambda d: mg.DTYPE_NAMES[d])
+@pytest.mark.parametrize("ta,tb", TRANS)
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_parity_ragged_shapes(dtype, ta, tb, shape):
+    m, n, k = shape
+    alpha, beta = _ab(dtype)
+    c = Case(dtype, ta, tb, m, n, k, alpha, beta, pad=3, seed=7)
+    print(f"case {c}", flush=True)
+    check(c, run_case(c))
+
+
+@pytest.mark.parametrize("dtype", ALL_DTYPES, ids=lambda d: mg.DTYPE_NAMES[d])
+@pytest.mark.parametrize("ta,tb", [("N", "N"), ("T", "T")])
+def test_parity_unaligned_operands(dtype, ta, tb):
+    # odd leading dimensions and a one-element offset: element-wise staging
+    c = Case(dtype, ta, tb, 99, 77, 131, *_ab(dtype), pad=1, misalign=1, seed=8)
+    print(f"case {c}", flush=True)
+    check(c, run_case(c))
+
+
+@pytest.mark.parametrize("dtype", ALL_DTYPES, ids=lambda d: mg.DTYPE_NAMES[d])
+def test_every_configuration_and_raster_order(dtype):
+    """The whole family computes the same C: exact on small integers."""
+    results = []
+    try:
+        for cfg in range(mg.num_configs(dtype)):
+            for order in (0, 1):
+                mg.force_config(dtype, cfg, order)
+                c = Case(dtype, "N", "N", 300, 260, 280, 1.0, 1.0, dist="ints", seed=9)
+                print(f"cfg {cfg} order {order} case {c}", flush=True)
+                r = run_case(c)
+                assert r["cfg"]["cfg"] == cfg and r["cfg"]["order"] == order
+                check(c, r)
+                ref = r["Cq"] if r.get("Cq") is not None else r["Cs"]
+                assert np.array_equal(r["C"], np.asarray(ref).astype(r["C"].dtype)), \
+                    f"not exact on integers: cfg {cfg} order {order}"
+                results.append(r["C"])
+    finally:
+        mg.force_config(dtype, -1, 0)
+    for r in results[1:]:
+        assert np.array_equal(r, results[0])
+
+
+@pytest.mark.parametrize("dtype", ALL_DTYPES, ids=lambda d: mg.DTYPE_NAMES[d])
+@pytest.mark.parametrize("ta,tb", TRANS)
+def test_identity_and_permutation_pins(dtype, ta, tb):
+    import torch
+    from gemm_cases import encode, stored
+    n = 96
+    rng = np.random.default_rng(5)
+    B = rng.integers(-8, 9, size=(n, 70)).astype(np.float32)
+    P = np.eye(n, dtype=np.float32)[rng.permutation(n)]
+    for A in (np.eye(n, dtype=np.float32), P):
+        As = stored(encode(A, dtype), ta, n)
+        Bs = stored(encode(B, dtype), tb, n if tb in "Tt" else 70)
+        out_t = torch.int32 if dtype == mg.GEMM_I8 else torch.float32
+        dC = torch.full((n, 70), 7, dtype=out_t, device="cuda")
+        mg.gemm(ta, tb, n, 70, n, 1, to_device(As), As.shape[1], to_device(Bs), Bs.shape[1], 0,
+                dC, 70, dtype)
+        torch.cuda.synchronize()
+        assert np.array_equal(dC.cpu().numpy(), (A @ B).astype(dC.cpu().numpy().dtype))
+
+
+@pytest.mark.parametrize("dtype", [mg.GEMM_F32, mg.GEMM_F32_BF16X3, mg.GEMM_BF16, mg.GEMM_I8])
+def test_blas_special_cases(dtype):
+    import torch
+    is_int = dtype == mg.GEMM_I8
+    ct = torch.int32 if is_int else torch.float32
+    m, n, k = 37, 29, 41
+    C0 = torch.arange(m * n, dtype=ct, device="cuda").reshape(m, n)
+    esz = {mg.GEMM_F32: 4, mg.GEMM_F32_BF16X3: 4, mg.GEMM_BF16: 2, mg.GEMM_I8: 1}[dtype]
+    nanbuf = torch.full((m * k * 4,), -1, dtype=torch.uint8, device="cuda")  # NaN patterns
+    # k == 0: C = beta * C (A, B not read)
+    C = C0.clone()
+    mg.gemm("N", "N", m, n, 0, 1, None, 1, None, n, 2, C, n, dtype)
+    torch.cuda.synchronize()
+    assert torch.equal(C, 2 * C0)
+    # alpha == 0: C = beta * C, A and B (NaN) not read
+    C = C0.clone()
+    mg.gemm("N", "N", m, n, k, 0, nanbuf, k, nanbuf, n, 3, C, n, dtype)
+    torch.cuda.synchronize()
+    assert torch.equal(C, 3 * C0)
+    # beta == 0: NaN in C is overwritten, not propagated
+    if not is_int:
+        C = torch.full((m, n), float("nan"), device="cuda")
+        A = torch.ones(m * k * 4 // esz, dtype=torch.float32, device="cuda")
+        if dtype == mg.GEMM_BF16:
+            A = torch.ones(m * k, dtype=torch.bfloat16, device="cuda")
+        B = torch.ones_like(A)
+        mg.gemm("N", "N", m, n, k, 1, A, k, B, n, 0, C, n, dtype)
+        torch.cuda.synchronize()
+        assert torch.equal(C, torch.full_like(C, float(k)))
+    # m == 0: nothing happens
+    mg.gemm("N", "N", 0, n, k, 1, None, k, None, n, 0, None, n, dtype)
+
+
+@pytest.mark.parametrize("dtype", [d for d in ALL_DTYPES if d != mg.GEMM_I8],
+                         ids=lambda d: mg.DTYPE_NAMES[d])
+def test_small_integers_exact_every_float_path(dtype):
+    c = Case(dtype, "N", "N", 200, 180, 1000, 1.0, 0.0, dist="ints", seed=10)
+    r = run_case(c)
+    ref = r["Cq"] if r.get("Cq") is not None else r["Cs"]
+    assert np.array_equal(r["C"].astype(np.float64), ref)
+
+
+def test_config1_full_fp32_256():
+    """C = A*B + C, m = n = k = 256, U[-1,1], plain FP32, compared in full."""
+    c = Case(mg.GEMM_F32, "N", "N", 256, 256, 256, 1.0, 1.0, seed=1)
+    r = run_case(c)
+    check(c, r)
+    assert r["err_source"] <= 2e-6
+
+
+SWEEP = [(1024, 1024, 1024), (2048, 2048, 2048), (4096, 4096, 4096), (8192, 8192, 8192),
+         (50176, 64, 576), (3136, 256, 2304), (196, 1024, 4608), (12544, 128, 1152)]
+
+
+def _sample(m, n, count=192, seed=3):
+    rng = np.random.default_rng(seed)
+    r = np.concatenate([rng.integers(0, m, count), [0, m - 1, m - 1, 0]])
+    q = np.concatenate([rng.integers(0, n, count), [0, n - 1, 0, n - 1]])
+    return r, q
+
+
+@pytest.mark.parametrize("shape", SWEEP, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("beta", [0.0, 1.0])
+def test_fp32_sweep_sampled(shape, beta):
+    m, n, k = shape
+    c = Case(mg.GEMM_F32, "N", "N", m, n, k, 1.0, beta, seed=2)
+    r = run_case(c, sample=_sample(m, n))
+    print(f"{shape} beta={beta} err={r['err_source']:.3g}", flush=True)
+    check(c, r)
+
+
+@pytest.mark.parametrize("dtype", [mg.GEMM_F32_BF16X3, mg.GEMM_F32_BF16X6, mg.GEMM_BF16,
+                                   mg.GEMM_F16, mg.GEMM_F8E4M3],
+                         ids=lambda d: mg.DTYPE_NAMES[d])
+@pytest.mark.parametrize("dist", ["normal", "badly_scaled"])
+def test_precision_8192_sampled(dtype, dist):
+    c = Case(dtype, "N", "N", 8192, 8192, 8192, 1.0, 0.0, dist=dist, seed=3)
+    r = run_case(c, sample=_sample(8192, 8192, 128))
+    print(f"{mg.DTYPE_NAMES[dtype]} {dist} err={r['err_source']:.3g}", flush=True)
+    if dist == "normal":
+        check(c, r)
+    elif dtype in (mg.GEMM_F32_BF16X3, mg.GEMM_F32_BF16X6):
+        # the split path keeps FP32 accuracy on badly scaled inputs as well
+        assert r["err_source"] <= 2e-6
+
+
+def test_int8_4096_sampled_exact():
+    c = Case(mg.GEMM_I8, "N", "N", 4096, 4096, 4096, 1.0, 1.0, seed=4)
+    r = run_case(c, sample=_sample(4096, 4096, 256))
+    check(c, r)
