@@ -126,15 +126,24 @@ int gemm_grouped(int64_t count, const gemm_problem *problems, int dtype);
 int64_t gemm_grouped_capacity(void);
 
 /*
- * Graph-capturable grouped launch.  gemm_grouped_capture_begin() returns (in
- * *slot) a host pointer to a pinned descriptor slot owned by the library;
- * the caller captures gemm_grouped_slot(slot, count, dtype) into a HIP graph
- * on its stream, and before each replay may rewrite the problem list with
- * gemm_grouped_slot_write(slot, count, problems, dtype) (which validates like
- * gemm_grouped).  A replay re-reads the slot's pinned memory, so rewrite it
- * only while no replay that uses it is in flight.
+ * Graph-capturable grouped launch.
+ *   gemm_grouped_slot_create(&slot, capacity): a library-owned descriptor slot
+ *     (pinned host table, device table, device counters) for up to `capacity`
+ *     problems (1 <= capacity <= gemm_grouped_capacity()).  Allocates; call it
+ *     outside any capture.
+ *   gemm_grouped_slot_write(slot, count, problems, dtype): validates like
+ *     gemm_grouped (errors -(1000*p + i)) and writes the table into the slot's
+ *     pinned memory.  The dtype family (FP32 / split / BF16 / FP16 / FP8 /
+ *     INT8) of a slot is fixed by its first write.  count <= capacity.
+ *   gemm_grouped_slot_launch(slot): enqueues, on the current stream, one copy
+ *     of the pinned table (header + capacity descriptors) to the device and
+ *     one persistent kernel launch whose grid does not depend on the table.
+ *     Capture this call into a HIP graph; each replay re-reads the pinned
+ *     table, so the problem list can be rewritten between replays.  Rewrite
+ *     a slot only while no launch or replay that uses it is in flight.
+ *   gemm_grouped_slot_destroy(slot): synchronises the slot's device and frees it.
  */
-int gemm_grouped_slot_create(void **slot);
+int gemm_grouped_slot_create(void **slot, int64_t capacity);
 int gemm_grouped_slot_write(void *slot, int64_t count, const gemm_problem *problems,
                             int dtype);
 int gemm_grouped_slot_launch(void *slot);

@@ -62,7 +62,7 @@ def lib():
     L.gemm_grouped.restype = _INT
     L.gemm_grouped_capacity.argtypes = []
     L.gemm_grouped_capacity.restype = _I64
-    L.gemm_grouped_slot_create.argtypes = [ctypes.POINTER(_P)]
+    L.gemm_grouped_slot_create.argtypes = [ctypes.POINTER(_P), _I64]
     L.gemm_grouped_slot_create.restype = _INT
     L.gemm_grouped_slot_write.argtypes = [_P, _I64, ctypes.POINTER(_Problem), _INT]
     L.gemm_grouped_slot_write.restype = _INT
@@ -187,10 +187,12 @@ def gemm_grouped_capacity() -> int:
 class GroupedSlot:
     """A library-owned descriptor slot whose launch can be captured in a HIP graph."""
 
-    def __init__(self):
+    def __init__(self, capacity: int = 1024):
         h = _P()
-        _check(lib().gemm_grouped_slot_create(ctypes.byref(h)), "gemm_grouped_slot_create")
+        _check(lib().gemm_grouped_slot_create(ctypes.byref(h), int(capacity)),
+               "gemm_grouped_slot_create")
         self.handle = h
+        self.capacity = int(capacity)
 
     def write(self, problems: Sequence[Problem], dtype: int, check: bool = True) -> int:
         rc = lib().gemm_grouped_slot_write(self.handle, len(problems), _problems(problems),

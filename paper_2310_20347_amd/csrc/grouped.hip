@@ -1,19 +1,390 @@
-// Grouped persistent launch (placeholder until the persistent kernel lands).
+// Host side of the grouped persistent launch: validation, per-problem plan
+// (tile shape from the tuning table's size bucket, transposition, raster
+// order), ordering of problems by descending per-tile cost so the longest
+// tiles start first, descriptor tables in pinned host memory copied to the
+// device on the launch stream, and the capturable slot API.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
 #include "abi_internal.hpp"
+#include "grouped.hpp"
 #include "mgemm.h"
 
 namespace mg {
-int grouped_device_init(DevState *) { return GEMM_OK; }
-void grouped_device_free(DevState *) {}
+
+GroupedFamily grouped_family_f32();
+GroupedFamily grouped_family_split();
+GroupedFamily grouped_family_bf16();
+GroupedFamily grouped_family_f16();
+GroupedFamily grouped_family_f8();
+GroupedFamily grouped_family_i8();
+
+GroupedFamily grouped_family(int fam)
+{
+    switch (fam) {
+    case G_F32: return grouped_family_f32();
+    case G_SPLIT: return grouped_family_split();
+    case G_BF16: return grouped_family_bf16();
+    case G_F16: return grouped_family_f16();
+    case G_F8: return grouped_family_f8();
+    case G_I8: return grouped_family_i8();
+    default: return GroupedFamily();
+    }
+}
+
+constexpr int64_t kCapacity = 8192;   // problems per descriptor table
+constexpr int kRotating = 4;          // rotating slots of gemm_grouped per device
+constexpr size_t kTableBytes = sizeof(GHeader) + kCapacity * sizeof(GDesc);
+
+struct Slot {
+    char *host = nullptr;     // pinned staging
+    char *dev = nullptr;      // device table
+    int *counters = nullptr;  // device {next tile, finished workgroups}
+    hipEvent_t done = nullptr;
+    bool used = false;
+    int family = -1;
+    int device = 0;
+    int64_t capacity = kCapacity;
+};
+
+struct GroupedDev {
+    GroupedFamily fam[G_NUM];
+    int grid[G_NUM] = {0, 0, 0, 0, 0, 0};
+    Slot rot[kRotating];
+    int next = 0;
+    std::mutex mu;
+};
+
+static int family_of(int dtype)
+{
+    switch (dtype) {
+    case GEMM_F32: return G_F32;
+    case GEMM_F32_BF16X3: case GEMM_F32_BF16X3_ONLY: case GEMM_F32_BF16X6: return G_SPLIT;
+    case GEMM_BF16: return G_BF16;
+    case GEMM_F16: return G_F16;
+    case GEMM_F8E4M3: return G_F8;
+    case GEMM_I8: return G_I8;
+    default: return -1;
+    }
+}
+
+static int slot_alloc(Slot &s, int device)
+{
+    hipError_t e;
+    s.device = device;
+    if ((e = hipHostMalloc((void **)&s.host, kTableBytes, hipHostMallocDefault)) != hipSuccess) goto fail;
+    if ((e = hipMalloc((void **)&s.dev, kTableBytes)) != hipSuccess) goto fail;
+    if ((e = hipMalloc((void **)&s.counters, 2 * sizeof(int))) != hipSuccess) goto fail;
+    if ((e = hipMemset(s.counters, 0, 2 * sizeof(int))) != hipSuccess) goto fail;
+    if ((e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess) goto fail;
+    if ((e = hipDeviceSynchronize()) != hipSuccess) goto fail;
+    return GEMM_OK;
+fail:
+    t_tls.hip_err = (int)e;
+    return GEMM_E_HIP;
+}
+
+static void slot_free(Slot &s)
+{
+    if (s.done) (void)hipEventSynchronize(s.done);
+    if (s.host) (void)hipHostFree(s.host);
+    if (s.dev) (void)hipFree(s.dev);
+    if (s.counters) (void)hipFree(s.counters);
+    if (s.done) (void)hipEventDestroy(s.done);
+    s = Slot();
+}
+
+int grouped_device_init(DevState *d)
+{
+    if (d->grouped_ready) return GEMM_OK;
+    std::lock_guard<std::mutex> g(g_mu);
+    if (d->grouped_ready) return GEMM_OK;
+    GroupedDev *gd = new GroupedDev();
+    for (int f = 0; f < G_NUM; ++f) {
+        gd->fam[f] = grouped_family(f);
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gd->fam[f].func, 256, 0);
+        if (e != hipSuccess || per_cu < 1) per_cu = 1;
+        gd->grid[f] = d->cus * per_cu;
+    }
+    for (int i = 0; i < kRotating; ++i) {
+        int rc = slot_alloc(gd->rot[i], d->device);
+        if (rc != GEMM_OK) {
+            for (int j = 0; j <= i; ++j) slot_free(gd->rot[j]);
+            delete gd;
+            return rc;
+        }
+    }
+    d->grouped = gd;
+    d->grouped_ready = true;
+    return GEMM_OK;
+}
+
+void grouped_device_free(DevState *d)
+{
+    if (!d->grouped_ready) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(d->device);
+    GroupedDev *gd = (GroupedDev *)d->grouped;
+    for (int i = 0; i < kRotating; ++i) slot_free(gd->rot[i]);
+    delete gd;
+    d->grouped = nullptr;
+    d->grouped_ready = false;
+    (void)hipSetDevice(cur);
+}
+
+static int ensure_grouped(DevState **out)
+{
+    ensure_registered();
+    DevState *d = nullptr;
+    int rc = device_state(&d);
+    if (rc != GEMM_OK) return rc;
+    rc = grouped_device_init(d);
+    if (rc != GEMM_OK) return rc;
+    *out = d;
+    return GEMM_OK;
+}
+
+// Builds the descriptor table of `count` problems into `table` (host memory).
+// Returns 0 / -(1000*p + i) / GEMM_E_*; sets total tiles in the header.
+static int build_table(const GroupedDev *gd, int cus, int64_t count, const gemm_problem *pr,
+                       int dtype, char *table)
+{
+    if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -3;
+    if (count < 0) return -1;
+    if (count > 0 && !pr) return -2;
+    if (count > kCapacity) return GEMM_E_WORKSPACE;
+    const int fam = family_of(dtype);
+    const GroupedFamily &F = gd->fam[fam];
+    for (int64_t p = 0; p < count; ++p) {
+        const gemm_problem &q = pr[p];
+        const int v = validate(q.transA, q.transB, q.m, q.n, q.k, q.alpha, q.A, q.lda, q.B, q.ldb,
+                               q.beta, q.C, q.ldc, dtype);
+        if (v != 0) return (int)(-1000 * p + v);
+        if (q.m > 0x7FFFFFFF || q.n > 0x7FFFFFFF || q.k > 0x7FFFFFFF) return GEMM_E_UNSUPPORTED;
+    }
+    GHeader *h = (GHeader *)table;
+    GDesc *descs = (GDesc *)(table + sizeof(GHeader));
+    std::vector<GDesc> tmp;
+    std::vector<double> cost;
+    tmp.reserve((size_t)count);
+    for (int64_t p = 0; p < count; ++p) {
+        const gemm_problem &q = pr[p];
+        if (q.m == 0 || q.n == 0) continue;
+        if ((q.alpha == 0.0 || q.k == 0) && q.beta == 1.0) continue;
+        const bool ta = q.transA == 'T' || q.transA == 't' || q.transA == 'C' || q.transA == 'c';
+        const bool tb = q.transB == 'T' || q.transB == 't' || q.transB == 'C' || q.transB == 'c';
+        const int trans = 2 * ta + tb;
+        const int kclass = kclass_of(dtype, q.k);
+        int cfg = 0, order = 0, group = 8;
+        select_config(kclass, trans, q.m, q.n, q.k, cus, cfg, order, group);
+        int shape;
+        if (kclass == K_SPLIT3)
+            shape = 2;
+        else
+            shape = (cfg == 0 || q.m < F.mc[1] || q.n < F.nc[1]) ? 0 : 1;
+        const int es = elem_bytes(kclass);
+        const bool vec = vec_ok(q.A, q.lda, es) && vec_ok(q.B, q.ldb, es);
+        if (!vec && shape == 1) shape = 0;
+        GDesc d;
+        std::memset(&d, 0, sizeof d);
+        GemmArgs &a = d.a;
+        a.A = q.A;
+        a.B = q.B;
+        a.C = q.C;
+        a.lda = q.lda;
+        a.ldb = q.ldb;
+        a.ldc = q.ldc;
+        a.m = (int)q.m;
+        a.n = (int)q.n;
+        a.k = (int)q.k;
+        a.alpha = (float)q.alpha;
+        a.beta = (float)q.beta;
+        a.ialpha = dtype == GEMM_I8 ? (int)q.alpha : 0;
+        a.ibeta = dtype == GEMM_I8 ? (int)q.beta : 0;
+        a.tiles_m = (int)((q.m + F.mc[shape] - 1) / F.mc[shape]);
+        a.tiles_n = (int)((q.n + F.nc[shape] - 1) / F.nc[shape]);
+        a.order = order;
+        a.group = std::max(1, group);
+        a.terms = split_terms(kclass);
+        d.body = shape * 8 + trans * 2 + (vec ? 1 : 0);
+        tmp.push_back(d);
+        // per-tile work: the k loop length times the tile area
+        const double kk = (q.alpha == 0.0) ? 0.0 : double(q.k);
+        cost.push_back((kk + 64.0) * F.mc[shape] * F.nc[shape]);
+    }
+    std::vector<size_t> idx(tmp.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+    int64_t tiles = 0;
+    for (size_t i = 0; i < idx.size(); ++i) {
+        GDesc d = tmp[idx[i]];
+        d.tile_start = (int)tiles;
+        tiles += int64_t(d.a.tiles_m) * d.a.tiles_n;
+        if (tiles > 0x7FFFFFFF) return GEMM_E_UNSUPPORTED;
+        descs[i] = d;
+    }
+    std::memset(h, 0, sizeof *h);
+    h->count = (int)idx.size();
+    h->total_tiles = (int)tiles;
+    h->family = fam;
+    return GEMM_OK;
+}
+
+static int launch_table(const GroupedDev *gd, const Slot &s, int fam, int grid, size_t bytes,
+                        hipStream_t st)
+{
+    hipError_t e = hipMemcpyAsync(s.dev, s.host, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) {
+        t_tls.hip_err = (int)e;
+        return GEMM_E_HIP;
+    }
+    const char *table = s.dev;
+    int *counters = s.counters;
+    void *args[] = {&table, &counters};
+    e = hipLaunchKernel(gd->fam[fam].func, dim3(grid), dim3(256), args, 0, st);
+    if (e != hipSuccess) {
+        t_tls.hip_err = (int)e;
+        return GEMM_E_HIP;
+    }
+    return GEMM_OK;
+}
+
 }  // namespace mg
 
+using namespace mg;
+
 extern "C" {
-int gemm_grouped(int64_t, const gemm_problem *, int) { return GEMM_E_UNSUPPORTED; }
-int64_t gemm_grouped_capacity(void) { return 0; }
-int gemm_grouped_slot_create(void **) { return GEMM_E_UNSUPPORTED; }
-int gemm_grouped_slot_write(void *, int64_t, const gemm_problem *, int) { return GEMM_E_UNSUPPORTED; }
-int gemm_grouped_slot_launch(void *) { return GEMM_E_UNSUPPORTED; }
-void gemm_grouped_slot_destroy(void *) {}
+
+int gemm_grouped(int64_t count, const gemm_problem *problems, int dtype)
+{
+    if (count < 0) return -1;
+    if (count > 0 && !problems) return -2;
+    if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -3;
+    if (count > kCapacity) return GEMM_E_WORKSPACE;
+    // validate before touching the device (same rules as gemm)
+    for (int64_t p = 0; p < count; ++p) {
+        const gemm_problem &q = problems[p];
+        const int v = validate(q.transA, q.transB, q.m, q.n, q.k, q.alpha, q.A, q.lda, q.B, q.ldb,
+                               q.beta, q.C, q.ldc, dtype);
+        if (v != 0) return (int)(-1000 * p + v);
+    }
+    if (count == 0) return GEMM_OK;
+    DevState *d = nullptr;
+    int rc = ensure_grouped(&d);
+    if (rc != GEMM_OK) return rc;
+    GroupedDev *gd = (GroupedDev *)d->grouped;
+    std::lock_guard<std::mutex> g(gd->mu);
+    Slot &s = gd->rot[gd->next];
+    gd->next = (gd->next + 1) % kRotating;
+    if (s.used) {
+        hipError_t e = hipEventSynchronize(s.done);   // previous copy from this slot consumed
+        if (e != hipSuccess) {
+            t_tls.hip_err = (int)e;
+            return GEMM_E_HIP;
+        }
+    }
+    rc = build_table(gd, d->cus, count, problems, dtype, s.host);
+    if (rc != GEMM_OK) return rc;
+    const GHeader *h = (const GHeader *)s.host;
+    if (h->total_tiles == 0) {
+        // only quick-return problems (C untouched)
+        return GEMM_OK;
+    }
+    const int fam = family_of(dtype);
+    const int grid = std::min(gd->grid[fam], h->total_tiles);
+    const size_t bytes = sizeof(GHeader) + size_t(h->count) * sizeof(GDesc);
+    hipStream_t st = t_tls.stream;
+    rc = launch_table(gd, s, fam, grid, bytes, st);
+    if (rc != GEMM_OK) return rc;
+    hipError_t e = hipEventRecord(s.done, st);
+    if (e != hipSuccess) {
+        t_tls.hip_err = (int)e;
+        return GEMM_E_HIP;
+    }
+    s.used = true;
+    return GEMM_OK;
 }
+
+int64_t gemm_grouped_capacity(void) { return kCapacity; }
+
+int gemm_grouped_slot_create(void **slot, int64_t capacity)
+{
+    if (!slot) return -1;
+    if (capacity < 1 || capacity > kCapacity) return -2;
+    DevState *d = nullptr;
+    int rc = ensure_grouped(&d);
+    if (rc != GEMM_OK) return rc;
+    Slot *s = new Slot();
+    rc = slot_alloc(*s, d->device);
+    if (rc != GEMM_OK) {
+        slot_free(*s);
+        delete s;
+        return rc;
+    }
+    std::memset(s->host, 0, sizeof(GHeader));
+    s->capacity = capacity;
+    *slot = s;
+    return GEMM_OK;
+}
+
+int gemm_grouped_slot_write(void *slot, int64_t count, const gemm_problem *problems, int dtype)
+{
+    if (!slot) return -1;
+    if (count < 0) return -2;
+    if (count > 0 && !problems) return -3;
+    if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -4;
+    Slot *s = (Slot *)slot;
+    if (count > s->capacity) return GEMM_E_WORKSPACE;
+    const int fam = family_of(dtype);
+    if (s->family >= 0 && s->family != fam) return GEMM_E_UNSUPPORTED;
+    DevState *d = nullptr;
+    int rc = ensure_grouped(&d);
+    if (rc != GEMM_OK) return rc;
+    // build into a private buffer first so a failed validation leaves the slot intact
+    std::vector<char> buf(sizeof(GHeader) + size_t(std::max<int64_t>(count, 0)) * sizeof(GDesc));
+    rc = build_table((GroupedDev *)d->grouped, d->cus, count, problems, dtype, buf.data());
+    if (rc != GEMM_OK) {
+        // a problem error is reported as in gemm_grouped: -(1000*p + i)
+        return rc;
+    }
+    const GHeader *h = (const GHeader *)buf.data();
+    std::memcpy(s->host, buf.data(), sizeof(GHeader) + size_t(h->count) * sizeof(GDesc));
+    s->family = fam;
+    return GEMM_OK;
+}
+
+int gemm_grouped_slot_launch(void *slot)
+{
+    if (!slot) return -1;
+    Slot *s = (Slot *)slot;
+    if (s->family < 0) return GEMM_E_UNSUPPORTED;   // never written
+    DevState *d = nullptr;
+    int rc = ensure_grouped(&d);
+    if (rc != GEMM_OK) return rc;
+    GroupedDev *gd = (GroupedDev *)d->grouped;
+    // the grid does not depend on the table, so a captured launch stays valid
+    // when the slot is rewritten; header + capacity descriptors are copied
+    const size_t bytes = sizeof(GHeader) + size_t(s->capacity) * sizeof(GDesc);
+    return launch_table(gd, *s, s->family, gd->grid[s->family], bytes, t_tls.stream);
+}
+
+void gemm_grouped_slot_destroy(void *slot)
+{
+    if (!slot) return;
+    Slot *s = (Slot *)slot;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(s->device);
+    (void)hipDeviceSynchronize();
+    slot_free(*s);
+    (void)hipSetDevice(cur);
+    delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Grouped persistent kernel: many independent GEMMs of uneven shapes in one
+// launch.  The host writes a descriptor table (one GemmArgs per problem plus
+// the compiled tile body to use and the problem's first global tile id).
+// Each workgroup repeatedly takes a global tile id, finds its problem by
+// binary search over the tile prefix, maps the local id through that
+// problem's raster order and runs the tile body (the same C-resident tile as
+// the single-GEMM kernel).  Tile ids beyond the first gridDim.x come from an
+// atomic counter; the last workgroup to finish resets the counters to zero,
+// so a launch leaves them ready for the next one (no memset node is needed,
+// which keeps the launch capturable in a graph).
+#pragma once
+
+#include "tile.hpp"
+
+namespace mg {
+
+struct GHeader {
+    int count;        // problems in the table
+    int total_tiles;  // sum of tiles over problems
+    int family;       // dtype family the table was built for
+    int pad[13];
+};
+
+struct GDesc {
+    GemmArgs a;
+    int body;         // shape * 8 + trans * 2 + vec
+    int tile_start;   // first global tile id of this problem
+    int pad[2];
+};
+static_assert(sizeof(GHeader) == 64, "header is 64 bytes");
+static_assert(sizeof(GDesc) % 16 == 0, "descriptors are 16-byte aligned");
+
+// A tile shape of a family: element type, mc x nc, LDS stages.
+template <class DT, int MC, int NC, int ST>
+struct Shape {
+    typedef DT dt;
+    static constexpr int mc = MC, nc = NC, st = ST;
+    static constexpr int lds = Tile<DT, MC, NC, 2, 2, false, false, true, ST>::LDS_BYTES;
+};
+struct NoShape {
+    static constexpr int lds = 0;
+};
+
+template <class S, bool VEC>
+__device__ __forceinline__ void run_shape(int trans, const GemmArgs &p, int tm, int tn, char *lds)
+{
+    typedef typename S::dt DT;
+    switch (trans) {
+    case 0: Tile<DT, S::mc, S::nc, 2, 2, false, false, VEC, S::st>::run(p, tm, tn, lds); break;
+    case 1: Tile<DT, S::mc, S::nc, 2, 2, false, true, VEC, S::st>::run(p, tm, tn, lds); break;
+    case 2: Tile<DT, S::mc, S::nc, 2, 2, true, false, VEC, S::st>::run(p, tm, tn, lds); break;
+    default: Tile<DT, S::mc, S::nc, 2, 2, true, true, VEC, S::st>::run(p, tm, tn, lds); break;
+    }
+}
+
+// Shapes 0 and 2 carry element-wise (unaligned) variants; shape 1 is vectorised only.
+template <class S0, class S1, class S2>
+__device__ __forceinline__ void run_body(int body, const GemmArgs &p, int tm, int tn, char *lds)
+{
+    const int shape = body >> 3, trans = (body >> 1) & 3, vec = body & 1;
+    if (shape == 0) {
+        if (vec) run_shape<S0, true>(trans, p, tm, tn, lds);
+        else run_shape<S0, false>(trans, p, tm, tn, lds);
+    } else if (shape == 1) {
+        run_shape<S1, true>(trans, p, tm, tn, lds);
+    } else {
+        if constexpr (S2::lds > 0) {
+            if (vec) run_shape<S2, true>(trans, p, tm, tn, lds);
+            else run_shape<S2, false>(trans, p, tm, tn, lds);
+        }
+    }
+}
+
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+template <class S0, class S1, class S2>
+__global__ void __launch_bounds__(256) grouped_kernel(const char *table, int *counters)
+{
+    __shared__ __attribute__((aligned(16))) char lds[cmax(cmax(S0::lds, S1::lds), S2::lds)];
+    __shared__ int s_next;
+    const GHeader *h = (const GHeader *)table;
+    const GDesc *descs = (const GDesc *)(table + sizeof(GHeader));
+    const int total = h->total_tiles, count = h->count;
+    int t = blockIdx.x;
+    while (t < total) {
+        int lo = 0, hi = count - 1;   // last problem whose first tile is <= t
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (descs[mid].tile_start <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const GemmArgs p = descs[lo].a;
+        const int body = descs[lo].body;
+        int tm, tn;
+        raster(t - descs[lo].tile_start, p.tiles_m, p.tiles_n, p.order, p.group, tm, tn);
+        run_body<S0, S1, S2>(body, p, tm, tn, lds);
+        if (threadIdx.x == 0) s_next = (int)gridDim.x + atomicAdd(&counters[0], 1);
+        __syncthreads();
+        t = __builtin_amdgcn_readfirstlane(s_next);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&counters[1], 1) == (int)gridDim.x - 1) {
+            atomicExch(&counters[0], 0);
+            atomicExch(&counters[1], 0);
+        }
+    }
+}
+
+// What the host needs to know about one family's kernel.
+struct GroupedFamily {
+    const void *func = nullptr;
+    int nshapes = 0;
+    int mc[3] = {0, 0, 0}, nc[3] = {0, 0, 0};
+    int lds = 0;
+};
+
+template <class S0, class S1, class S2>
+GroupedFamily make_family()
+{
+    GroupedFamily f;
+    f.func = (const void *)&grouped_kernel<S0, S1, S2>;
+    f.mc[0] = S0::mc;
+    f.nc[0] = S0::nc;
+    f.mc[1] = S1::mc;
+    f.nc[1] = S1::nc;
+    f.nshapes = 2;
+    if constexpr (S2::lds > 0) {
+        f.mc[2] = S2::mc;
+        f.nc[2] = S2::nc;
+        f.nshapes = 3;
+    }
+    f.lds = cmax(cmax(S0::lds, S1::lds), S2::lds);
+    return f;
+}
+
+enum GFam { G_F32 = 0, G_SPLIT, G_BF16, G_F16, G_F8, G_I8, G_NUM };
+GroupedFamily grouped_family(int fam);
+
+}  // namespace mg

@@ -1,0 +1,12 @@
+// Grouped persistent kernel of the split family (see grouped.hpp).  Shape 0 is
+// a 64x64 tile with element-wise variants for unaligned operands, shape 1 a
+// 128x128 tile; shape 2 is the six-term split at 64x64.
+#include "grouped.hpp"
+
+namespace mg {
+GroupedFamily grouped_family_split()
+{
+    return make_family<Shape<TSplit<2>, 64, 64, 2>, Shape<TSplit<2>, 128, 128, 1>,
+                       Shape<TSplit<3>, 64, 64, 1>>();
+}
+}  // namespace mg
