@@ -107,3 +107,20 @@ def test_no_device_reports_noinit():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     assert call() == 3
+
+
+def test_grouped_validation_before_device():
+    P = mg._binding._Problem
+    arr = (P * 3)()
+    for i in range(3):
+        arr[i] = P(b"N", b"N", 4, 5, 3, 1.0, 0x1000, 3, 0x2000, 5, 0.0, 0x3000, 5)
+    arr[2].ldb = 4                                   # problem 2, argument 10
+    assert mg.lib().gemm_grouped(3, arr, mg.GEMM_F32) == -(1000 * 2 + 10)
+    arr[2].ldb = 5
+    arr[0].transA = b"x"                             # problem 0, argument 1
+    assert mg.lib().gemm_grouped(3, arr, mg.GEMM_F32) == -1
+    assert mg.lib().gemm_grouped(-1, arr, mg.GEMM_F32) == -1
+    assert mg.lib().gemm_grouped(3, None, mg.GEMM_F32) == -2
+    assert mg.lib().gemm_grouped(3, arr, 42) == -3
+    assert mg.lib().gemm_grouped(0, None, mg.GEMM_F32) == 0
+    assert mg.gemm_grouped_capacity() >= 512
