@@ -180,6 +180,10 @@ def main():
     }
     if not args.profile_only and not args.no_extras:
         out["paths"] = extras(mg, torch, stream, ops)
+        del ops
+        torch.cuda.empty_cache()
+        out["grouped"] = grouped_bench(mg, torch, stream)
+        out["serving"] = serving_bench(mg, torch)
     if not args.profile_only and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
@@ -252,6 +256,101 @@ def extras(mg, torch, stream, ops):
                   "mfma_util": round(2.0 * n ** 3 / ms / 1e9 / 5033.0, 4)}
     res["precision_8192"] = prec
     return res
+
+
+def _dev_uniform(torch, shape, seed, dtype):
+    """Seeded operands generated on the device (torch's generator)."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    if dtype == "i8":
+        return torch.randint(-128, 128, shape, generator=g, device="cuda", dtype=torch.int8)
+    x = torch.rand(shape, generator=g, device="cuda", dtype=torch.float32) * 2 - 1
+    return x.to(torch.bfloat16) if dtype == "bf16" else x
+
+
+def grouped_bench(mg, torch, stream, reps=10):
+    """The batching workload: 512 GEMMs with m, n, k log-uniform on [16, 4096]
+    in one persistent launch; FP32-accurate split product and INT8."""
+    from paper_2310_20347_amd import inputs
+    shapes = inputs.log_uniform_shapes(512, 0)
+    out = {}
+    for name, dt, es, peak in (("bf16x3", mg.GEMM_F32_BF16X3, 4, 2516.6),
+                               ("i8", mg.GEMM_I8, 1, 5033.0)):
+        probs, keep = [], []
+        floor_s = 0.0
+        flops = 0.0
+        for i, (m, n, k) in enumerate(shapes):
+            q = 16 // es
+            lda, ldb = -(-k // q) * q, -(-n // q) * q
+            A = _dev_uniform(torch, (m, lda), 10 + 2 * i, "i8" if es == 1 else "f32")
+            B = _dev_uniform(torch, (k, ldb), 11 + 2 * i, "i8" if es == 1 else "f32")
+            C = torch.empty((m, n), dtype=torch.int32 if es == 1 else torch.float32,
+                            device="cuda")
+            keep.append((A, B, C))
+            probs.append(mg.Problem("N", "N", m, n, k, 1, A, lda, B, ldb, 0, C, n))
+            terms = 3 if (es == 4 and k >= 64) else (6 if es == 4 else 1)
+            f = 2.0 * m * n * k
+            flops += f
+            nbytes = es * (m * k + k * n) + 4 * m * n
+            floor_s += max(terms * f / (peak * 1e12), nbytes / (HBM_PEAK_GBS * 1e9))
+        torch.cuda.synchronize()
+        ms = []
+        for r in range(reps + 2):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            mg.gemm_grouped(probs, dt, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if r >= 2:
+                ms.append(e0.elapsed_time(e1))
+        p50 = float(np.percentile(ms, 50))
+        out[name] = {"problems": 512, "tflop": round(flops / 1e12, 4),
+                     "p50_ms": round(p50, 4), "p99_ms": round(float(np.percentile(ms, 99)), 4),
+                     "tflops": round(flops / (p50 * 1e-3) / 1e12, 2),
+                     "roofline_floor_ms": round(floor_s * 1e3, 4),
+                     "frac_of_grouped_roofline": round(floor_s * 1e3 / p50, 4)}
+        del keep, probs
+        torch.cuda.empty_cache()
+    return out
+
+
+def serving_bench(mg, torch, rates=(2000, 5000, 10000, 20000), count=3000, warmup=300):
+    """The serving workload: Poisson arrivals, shapes as the batching workload,
+    dtype mix 50% split-product FP32 / 30% BF16 / 20% INT8, 64 GiB budget."""
+    from paper_2310_20347_amd import inputs
+    from paper_2310_20347_amd import serve as sv
+    pool_bytes = 128 << 20
+    pools = {mg.GEMM_F32_BF16X3: _dev_uniform(torch, (pool_bytes // 4,), 77, "f32"),
+             mg.GEMM_BF16: _dev_uniform(torch, (pool_bytes // 2,), 78, "bf16"),
+             mg.GEMM_I8: _dev_uniform(torch, (pool_bytes,), 79, "i8")}
+    mix = (mg.GEMM_F32_BF16X3, mg.GEMM_BF16, mg.GEMM_I8)
+    names = {mg.GEMM_F32_BF16X3: "bf16x3", mg.GEMM_BF16: "bf16", mg.GEMM_I8: "i8"}
+    out = {}
+    for rate in rates:
+        n = count + warmup
+        seed = inputs.seed_for(5, "serve") + rate
+        shapes = inputs.log_uniform_shapes(n, seed)
+        arr = inputs.poisson_arrivals(n, float(rate), seed + 1)
+        kinds = inputs.categorical(n, [0.5, 0.3, 0.2], seed + 2)
+        reqs = []
+        for (m, nn, k), t, c in zip(shapes, arr, kinds):
+            dt = mix[c]
+            reqs.append(sv.Request(float(t), m, nn, k, dt, pools[dt].data_ptr(),
+                                   pools[dt].data_ptr(), None))
+        cfg = sv.config(budget_bytes=64 << 30, max_active=512, warmup_requests=warmup)
+        rc, st, _ = sv.serve_run(cfg, reqs)
+        out[str(rate)] = {
+            "offered_req_per_s": rate, "req_per_s": round(st.req_per_s, 1),
+            "tflops": round(st.tflops, 3), "p50_ms": round(st.p50_ms, 4),
+            "p99_ms": round(st.p99_ms, 4), "max_ms": round(st.max_ms, 3),
+            "completed": st.completed, "failed": st.failed, "rejected": st.rejected,
+            "req_per_launch": round(st.mean_requests_per_launch, 2),
+            "peak_arena_gb": round(st.peak_arena_bytes / 1e9, 3),
+            "by_dtype": {names[d]: {"count": st.count_by_dtype[d],
+                                    "p50_ms": round(st.p50_ms_by_dtype[d], 4),
+                                    "p99_ms": round(st.p99_ms_by_dtype[d], 4)} for d in mix}}
+    return out
 
 
 if __name__ == "__main__":

@@ -1,0 +1,632 @@
+// Serving loop: continuous batching of GEMM requests under an HBM budget.
+//
+// One host thread runs the scheduler.  Arrivals go to a FIFO queue; the head
+// is admitted when a slot is free and the arena (first-fit, coalescing free
+// list over one device allocation) can hold its operands.  Each step takes a
+// row panel chunk of C from every active request (oldest first), groups the
+// chunks by dtype and issues one grouped persistent launch per dtype on that
+// dtype's stream; up to `inflight_steps` launches per stream are in flight.
+// Completions are observed by polling events; a request's memory is released
+// when its last launch has retired.  The scheduler talks to a Backend: the
+// real one (HIP) or a simulated one (virtual clock, cost model, forced
+// failures) used by the CPU tests.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <limits>
+#include <map>
+#include <thread>
+#include <vector>
+
+#include "abi_internal.hpp"
+#include "mgemm.h"
+#include "mgemm_serve.h"
+
+namespace mg {
+namespace {
+
+constexpr int64_t kPanel = 128;     // rows of C per chunk unit (one tile row)
+constexpr int64_t kAlign = 256;     // arena alignment
+constexpr double kInf = std::numeric_limits<double>::infinity();
+
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+int in_bytes(int dtype)
+{
+    switch (dtype) {
+    case GEMM_BF16: case GEMM_F16: return 2;
+    case GEMM_F8E4M3: case GEMM_I8: return 1;
+    default: return 4;
+    }
+}
+
+struct Req {
+    int64_t idx = 0;
+    const serve_request *in = nullptr;
+    int64_t lda = 0, ldb = 0, ldc = 0, a_bytes = 0, b_bytes = 0, bytes = 0;
+    int64_t off = -1;
+    int64_t rows_issued = 0;
+    int outstanding = 0;
+    bool finished = false, failed = false, released = false, counted = false;
+    double admit_t = -1, done_t = -1;
+    int status = 0;
+};
+
+struct Launch {
+    int dtype = 0, slot = 0;
+    int64_t index = 0;
+    std::vector<int64_t> reqs, finishing;
+    double t_launch = 0, done_at = kInf;   // done_at: simulated completion
+    bool failed = false;
+};
+
+class Arena {
+public:
+    void init(int64_t size)
+    {
+        free_.clear();
+        if (size > 0) free_[0] = size;
+        used_ = peak_ = 0;
+    }
+    int64_t alloc(int64_t bytes)
+    {
+        bytes = round_up(bytes, kAlign);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const int64_t off = it->first, rem = it->second - bytes;
+                free_.erase(it);
+                if (rem > 0) free_[off + bytes] = rem;
+                used_ += bytes;
+                peak_ = std::max(peak_, used_);
+                return off;
+            }
+        }
+        return -1;
+    }
+    void release(int64_t off, int64_t bytes)
+    {
+        bytes = round_up(bytes, kAlign);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    int64_t peak() const { return peak_; }
+
+private:
+    std::map<int64_t, int64_t> free_;
+    int64_t used_ = 0, peak_ = 0;
+};
+
+class Backend {
+public:
+    virtual ~Backend() {}
+    virtual int begin(const serve_config &cfg) = 0;
+    virtual void end() = 0;
+    virtual double now() = 0;
+    virtual void idle_until(double t) = 0;
+    virtual char *base() = 0;
+    virtual int admit(const Req &r) = 0;
+    virtual int launch(Launch &l, const std::vector<gemm_problem> &probs) = 0;
+    virtual int query(Launch &l) = 0;   // 1 done, 0 pending, < 0 error
+    virtual double completion_hint() = 0;
+    virtual void fetch(const Req &r) = 0;
+};
+
+// ---------------------------------------------------------------------------
+// Real device.
+// ---------------------------------------------------------------------------
+class HipBackend : public Backend {
+public:
+    int begin(const serve_config &cfg) override
+    {
+        t0_ = std::chrono::steady_clock::now();
+        hipError_t e = hipMalloc((void **)&base_, (size_t)std::max<int64_t>(cfg.budget_bytes, kAlign));
+        if (e != hipSuccess) return fail(e);
+        slots_per_dtype_ = cfg.inflight_steps;
+        for (int d = 0; d < GEMM_NUM_DTYPES; ++d) {
+            if ((e = hipStreamCreate(&stream_[d])) != hipSuccess) return fail(e);
+            for (int s = 0; s < slots_per_dtype_; ++s) {
+                int rc = gemm_grouped_slot_create(&slot_[d][s], cfg.max_active);
+                if (rc != GEMM_OK) return rc;
+                if ((e = hipEventCreateWithFlags(&ev_[d][s], hipEventDisableTiming)) != hipSuccess)
+                    return fail(e);
+            }
+        }
+        return GEMM_OK;
+    }
+    void end() override
+    {
+        (void)hipDeviceSynchronize();
+        for (int d = 0; d < GEMM_NUM_DTYPES; ++d) {
+            for (int s = 0; s < slots_per_dtype_; ++s) {
+                if (slot_[d][s]) gemm_grouped_slot_destroy(slot_[d][s]);
+                if (ev_[d][s]) (void)hipEventDestroy(ev_[d][s]);
+                slot_[d][s] = nullptr;
+                ev_[d][s] = nullptr;
+            }
+            if (stream_[d]) (void)hipStreamDestroy(stream_[d]);
+            stream_[d] = nullptr;
+        }
+        if (base_) (void)hipFree(base_);
+        base_ = nullptr;
+    }
+    double now() override
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count();
+    }
+    void idle_until(double t) override
+    {
+        // completions are polled, so never sleep long
+        const double dt = std::min(t - now(), 20e-6);
+        if (dt > 2e-6) std::this_thread::sleep_for(std::chrono::duration<double>(dt));
+        else std::this_thread::yield();
+    }
+    char *base() override { return base_; }
+    int admit(const Req &r) override
+    {
+        hipStream_t s = stream_[r.in->dtype];
+        hipError_t e = hipMemcpyAsync(base_ + r.off, r.in->a_src, (size_t)(r.in->m * r.lda * in_bytes(r.in->dtype)),
+                                      hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(base_ + r.off + r.a_bytes, r.in->b_src,
+                               (size_t)(r.in->k * r.ldb * in_bytes(r.in->dtype)), hipMemcpyDeviceToDevice, s);
+        return e == hipSuccess ? GEMM_OK : fail(e);
+    }
+    int launch(Launch &l, const std::vector<gemm_problem> &probs) override
+    {
+        void *slot = slot_[l.dtype][l.slot];
+        int rc = gemm_grouped_slot_write(slot, (int64_t)probs.size(), probs.data(), l.dtype);
+        if (rc != GEMM_OK) return rc;
+        hipStream_t saved = t_tls.stream;
+        t_tls.stream = stream_[l.dtype];
+        rc = gemm_grouped_slot_launch(slot);
+        t_tls.stream = saved;
+        if (rc != GEMM_OK) return rc;
+        hipError_t e = hipEventRecord(ev_[l.dtype][l.slot], stream_[l.dtype]);
+        return e == hipSuccess ? GEMM_OK : fail(e);
+    }
+    int query(Launch &l) override
+    {
+        hipError_t e = hipEventQuery(ev_[l.dtype][l.slot]);
+        if (e == hipSuccess) return 1;
+        if (e == hipErrorNotReady) return 0;
+        t_tls.hip_err = (int)e;
+        return -1;
+    }
+    double completion_hint() override { return kInf; }
+    void fetch(const Req &r) override
+    {
+        if (!r.in->result) return;
+        (void)hipMemcpy(r.in->result, base_ + r.off + r.a_bytes + r.b_bytes,
+                        (size_t)(r.in->m * r.ldc * 4), hipMemcpyDeviceToHost);
+    }
+
+private:
+    int fail(hipError_t e)
+    {
+        t_tls.hip_err = (int)e;
+        return GEMM_E_HIP;
+    }
+    std::chrono::steady_clock::time_point t0_;
+    char *base_ = nullptr;
+    hipStream_t stream_[GEMM_NUM_DTYPES] = {};
+    void *slot_[GEMM_NUM_DTYPES][4] = {};
+    hipEvent_t ev_[GEMM_NUM_DTYPES][4] = {};
+    int slots_per_dtype_ = 0;
+};
+
+// ---------------------------------------------------------------------------
+// Simulated device: virtual time, one in-order queue per dtype.
+// ---------------------------------------------------------------------------
+class SimBackend : public Backend {
+public:
+    explicit SimBackend(const serve_sim &s) : sim_(s) {}
+    int begin(const serve_config &) override
+    {
+        t_ = 0;
+        for (double &f : stream_free_) f = 0;
+        return GEMM_OK;
+    }
+    void end() override {}
+    double now() override { return t_; }
+    void idle_until(double t) override { t_ = std::max(t_, t); }
+    char *base() override { return nullptr; }
+    int admit(const Req &) override { return GEMM_OK; }
+    int launch(Launch &l, const std::vector<gemm_problem> &probs) override
+    {
+        const int64_t idx = count_++;
+        if (idx == sim_.fail_launch) return GEMM_E_HIP;
+        double cost = sim_.launch_overhead_s;
+        for (const gemm_problem &p : probs) {
+            const double flops = 2.0 * p.m * p.n * p.k;
+            const double bytes = double(in_bytes(l.dtype)) * (p.m * p.k + p.k * p.n) + 4.0 * p.m * p.n;
+            cost += std::max(flops / sim_.flops_per_s, bytes / sim_.bytes_per_s);
+        }
+        const double start = std::max(t_, stream_free_[l.dtype]);
+        l.done_at = (idx == sim_.hang_launch) ? kInf : start + cost;
+        stream_free_[l.dtype] = l.done_at;
+        pending_.push_back(&l);
+        return GEMM_OK;
+    }
+    int query(Launch &l) override
+    {
+        if (t_ >= l.done_at) {
+            pending_.erase(std::remove(pending_.begin(), pending_.end(), &l), pending_.end());
+            return 1;
+        }
+        return 0;
+    }
+    double completion_hint() override
+    {
+        double h = kInf;
+        for (Launch *l : pending_) h = std::min(h, l->done_at);
+        return h;
+    }
+    void fetch(const Req &) override {}
+
+private:
+    serve_sim sim_;
+    double t_ = 0;
+    double stream_free_[GEMM_NUM_DTYPES] = {};
+    int64_t count_ = 0;
+    std::vector<Launch *> pending_;
+};
+
+// ---------------------------------------------------------------------------
+// Scheduler.
+// ---------------------------------------------------------------------------
+double percentile(std::vector<double> v, double q)
+{
+    if (v.empty()) return -1.0;
+    std::sort(v.begin(), v.end());
+    const double pos = q * double(v.size() - 1);
+    const size_t lo = (size_t)std::floor(pos), hi = (size_t)std::ceil(pos);
+    return v[lo] + (v[hi] - v[lo]) * (pos - double(lo));
+}
+
+int check_config(const serve_config *cfg)
+{
+    if (!cfg) return -1;
+    if (cfg->budget_bytes <= 0 || cfg->max_active < 1 || cfg->max_active > 8192 ||
+        cfg->step_tile_budget < 1 || cfg->request_tile_cap < 1 || cfg->inflight_steps < 1 ||
+        cfg->inflight_steps > 4 || !(cfg->watchdog_s > 0) || cfg->warmup_requests < 0)
+        return -1;
+    return 0;
+}
+
+int check_requests(int64_t count, const serve_request *reqs, bool need_src)
+{
+    if (count < 0) return -2;
+    if (count > 0 && !reqs) return -3;
+    for (int64_t i = 0; i < count; ++i) {
+        const serve_request &r = reqs[i];
+        if (r.m <= 0 || r.n <= 0 || r.k <= 0 || r.m > 0x7FFFFFFF || r.n > 0x7FFFFFFF ||
+            r.k > 0x7FFFFFFF || r.dtype < 0 || r.dtype >= GEMM_NUM_DTYPES ||
+            !std::isfinite(r.arrival_s) || r.arrival_s < 0 ||
+            (need_src && (!r.a_src || !r.b_src)))
+            return -3;
+    }
+    return 0;
+}
+
+int run(Backend &be, const serve_config &cfg, int64_t count, const serve_request *reqs,
+        serve_stats *stats, serve_outcome *outcomes)
+{
+    std::vector<Req> R((size_t)count);
+    for (int64_t i = 0; i < count; ++i) {
+        Req &r = R[(size_t)i];
+        r.idx = i;
+        r.in = &reqs[i];
+        serve_layout(r.in->m, r.in->n, r.in->k, r.in->dtype, &r.lda, &r.ldb, &r.ldc, &r.bytes);
+        r.a_bytes = round_up(r.in->m * r.lda * in_bytes(r.in->dtype), kAlign);
+        r.b_bytes = round_up(r.in->k * r.ldb * in_bytes(r.in->dtype), kAlign);
+    }
+    std::vector<int64_t> order((size_t)count);
+    for (int64_t i = 0; i < count; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
+
+    int rc = be.begin(cfg);
+    if (rc != GEMM_OK) {
+        be.end();
+        return rc;
+    }
+    Arena arena;
+    arena.init(cfg.budget_bytes);
+    std::deque<int64_t> queue;
+    std::vector<int64_t> active;             // admission order
+    std::list<Launch> inflight;              // launch records (stable addresses)
+    int inflight_per[GEMM_NUM_DTYPES] = {};
+    int next_slot[GEMM_NUM_DTYPES] = {};
+    size_t next_arrival = 0;
+    int64_t done = 0, launches = 0, steps = 0, peak_active = 0, reqs_in_launches = 0;
+    int result = GEMM_OK;
+
+    auto finish_req = [&](Req &r) {
+        if (!r.counted) {
+            r.counted = true;
+            ++done;
+        }
+        if (r.outstanding == 0 && !r.released && r.off >= 0) {
+            arena.release(r.off, r.bytes);
+            r.released = true;
+            active.erase(std::remove(active.begin(), active.end(), r.idx), active.end());
+        }
+    };
+
+    while (done < count) {
+        const double now = be.now();
+        while (next_arrival < order.size() && reqs[order[next_arrival]].arrival_s <= now)
+            queue.push_back(order[next_arrival++]);
+        // admission: FIFO, head of line waits for a slot and arena space
+        while (!queue.empty() && (int64_t)active.size() < cfg.max_active) {
+            Req &r = R[(size_t)queue.front()];
+            if (round_up(r.bytes, kAlign) > cfg.budget_bytes) {
+                r.status = GEMM_E_WORKSPACE;
+                queue.pop_front();
+                finish_req(r);
+                continue;
+            }
+            const int64_t off = arena.alloc(r.bytes);
+            if (off < 0) break;
+            r.off = off;
+            r.admit_t = now;
+            queue.pop_front();
+            active.push_back(r.idx);
+            peak_active = std::max<int64_t>(peak_active, (int64_t)active.size());
+            if (be.admit(r) != GEMM_OK) {
+                r.failed = true;
+                r.status = GEMM_E_SERVE;
+                finish_req(r);
+            }
+        }
+        bool progressed = false;
+        // retire finished launches: in launch order within a dtype stream (a
+        // later launch of a stream is not retired before an earlier one), any
+        // order across streams
+        bool blocked[GEMM_NUM_DTYPES] = {};
+        for (auto it = inflight.begin(); it != inflight.end();) {
+            Launch &l = *it;
+            const int q = blocked[l.dtype] ? 0 : be.query(l);
+            if (q == 0) {
+                blocked[l.dtype] = true;
+                if (now - l.t_launch > cfg.watchdog_s) {
+                    result = GEMM_E_SERVE;
+                    break;
+                }
+                ++it;
+                continue;
+            }
+            for (int64_t ri : l.reqs) {
+                Req &r = R[(size_t)ri];
+                --r.outstanding;
+                if (q < 0) {
+                    r.failed = true;
+                    r.status = GEMM_E_SERVE;
+                }
+            }
+            for (int64_t ri : l.finishing) {
+                Req &r = R[(size_t)ri];
+                if (!r.failed) {
+                    r.finished = true;
+                    r.done_t = be.now();
+                    be.fetch(r);
+                }
+            }
+            for (int64_t ri : l.reqs) {
+                Req &r = R[(size_t)ri];
+                if (r.finished || r.failed) finish_req(r);
+            }
+            --inflight_per[l.dtype];
+            it = inflight.erase(it);
+            progressed = true;
+        }
+        if (result != GEMM_OK) break;
+        // one step: a chunk from every active request with work left
+        std::vector<gemm_problem> probs[GEMM_NUM_DTYPES];
+        std::vector<int64_t> who[GEMM_NUM_DTYPES], last[GEMM_NUM_DTYPES];
+        int64_t step_tiles = 0;
+        for (int64_t ri : active) {
+            Req &r = R[(size_t)ri];
+            const int dt = r.in->dtype;
+            if (r.failed || r.rows_issued >= r.in->m || inflight_per[dt] >= cfg.inflight_steps) continue;
+            const int64_t tpp = (r.in->n + kPanel - 1) / kPanel;   // tiles per row panel
+            const int64_t cap_rows = std::max<int64_t>(1, cfg.request_tile_cap / tpp) * kPanel;
+            const int64_t rows = std::min(r.in->m - r.rows_issued, cap_rows);
+            const int64_t tiles = (rows + kPanel - 1) / kPanel * tpp;
+            if (step_tiles > 0 && step_tiles + tiles > cfg.step_tile_budget) break;
+            step_tiles += tiles;
+            char *b = be.base();
+            const int es = in_bytes(dt);
+            gemm_problem p;
+            std::memset(&p, 0, sizeof p);
+            p.transA = 'N';
+            p.transB = 'N';
+            p.m = rows;
+            p.n = r.in->n;
+            p.k = r.in->k;
+            p.alpha = 1.0;
+            p.beta = 0.0;
+            p.lda = r.lda;
+            p.ldb = r.ldb;
+            p.ldc = r.ldc;
+            if (b) {
+                p.A = b + r.off + r.rows_issued * r.lda * es;
+                p.B = b + r.off + r.a_bytes;
+                p.C = b + r.off + r.a_bytes + r.b_bytes + r.rows_issued * r.ldc * 4;
+            }
+            r.rows_issued += rows;
+            probs[dt].push_back(p);
+            who[dt].push_back(ri);
+            if (r.rows_issued >= r.in->m) last[dt].push_back(ri);
+        }
+        bool stepped = false;
+        for (int dt = 0; dt < GEMM_NUM_DTYPES; ++dt) {
+            if (probs[dt].empty()) continue;
+            inflight.emplace_back();
+            Launch &l = inflight.back();
+            l.dtype = dt;
+            l.slot = next_slot[dt];
+            next_slot[dt] = (next_slot[dt] + 1) % cfg.inflight_steps;
+            l.index = launches++;
+            l.reqs = who[dt];
+            l.finishing = last[dt];
+            l.t_launch = be.now();
+            for (int64_t ri : l.reqs) ++R[(size_t)ri].outstanding;
+            reqs_in_launches += (int64_t)l.reqs.size();
+            ++inflight_per[dt];
+            stepped = true;
+            if (be.launch(l, probs[dt]) != GEMM_OK) {
+                // the launch did not start: its requests fail, the loop goes on
+                for (int64_t ri : l.reqs) {
+                    Req &r = R[(size_t)ri];
+                    --r.outstanding;
+                    r.failed = true;
+                    r.status = GEMM_E_SERVE;
+                    finish_req(r);
+                }
+                --inflight_per[dt];
+                inflight.pop_back();
+            }
+        }
+        if (stepped) {
+            ++steps;
+            progressed = true;
+        }
+        if (!progressed && done < count) {
+            double t_next = be.now() + 1e-4;
+            if (next_arrival < order.size())
+                t_next = std::min(t_next, reqs[order[next_arrival]].arrival_s);
+            t_next = std::min(t_next, be.completion_hint());
+            be.idle_until(std::max(t_next, be.now()));
+        }
+    }
+    be.end();
+
+    // statistics
+    std::vector<double> lat, lat_by[GEMM_NUM_DTYPES];
+    double t_first = kInf, t_last = 0, flops = 0;
+    int64_t completed = 0, failed = 0, rejected = 0;
+    for (size_t pos = 0; pos < order.size(); ++pos) {
+        const Req &r = R[(size_t)order[pos]];
+        if (r.finished) ++completed;
+        else if (r.status == GEMM_E_WORKSPACE) ++rejected;
+        else ++failed;
+        if (outcomes) {
+            serve_outcome &o = outcomes[r.idx];
+            o.admit_s = r.admit_t;
+            o.done_s = r.finished ? r.done_t : -1.0;
+            o.latency_ms = r.finished ? 1e3 * (r.done_t - r.in->arrival_s) : -1.0;
+            o.status = r.finished ? 0 : (r.status ? r.status : GEMM_E_SERVE);
+        }
+        if ((int64_t)pos < cfg.warmup_requests || !r.finished) continue;
+        const double ms = 1e3 * (r.done_t - r.in->arrival_s);
+        lat.push_back(ms);
+        lat_by[r.in->dtype].push_back(ms);
+        t_first = std::min(t_first, r.in->arrival_s);
+        t_last = std::max(t_last, r.done_t);
+        flops += 2.0 * r.in->m * r.in->n * r.in->k;
+    }
+    if (stats) {
+        std::memset(stats, 0, sizeof *stats);
+        stats->completed = completed;
+        stats->failed = failed;
+        stats->rejected = rejected;
+        stats->measured = (int64_t)lat.size();
+        stats->window_s = lat.empty() ? 0.0 : t_last - t_first;
+        stats->req_per_s = stats->window_s > 0 ? lat.size() / stats->window_s : 0.0;
+        stats->tflops = stats->window_s > 0 ? flops / stats->window_s / 1e12 : 0.0;
+        stats->p50_ms = percentile(lat, 0.50);
+        stats->p99_ms = percentile(lat, 0.99);
+        double sum = 0, mx = 0;
+        for (double v : lat) {
+            sum += v;
+            mx = std::max(mx, v);
+        }
+        stats->mean_ms = lat.empty() ? -1.0 : sum / lat.size();
+        stats->max_ms = lat.empty() ? -1.0 : mx;
+        for (int d = 0; d < GEMM_NUM_DTYPES; ++d) {
+            stats->count_by_dtype[d] = (int64_t)lat_by[d].size();
+            stats->p50_ms_by_dtype[d] = percentile(lat_by[d], 0.50);
+            stats->p99_ms_by_dtype[d] = percentile(lat_by[d], 0.99);
+        }
+        stats->steps = steps;
+        stats->launches = launches;
+        stats->peak_arena_bytes = arena.peak();
+        stats->peak_active = peak_active;
+        stats->mean_requests_per_launch = launches ? double(reqs_in_launches) / launches : 0.0;
+    }
+    return result;
+}
+
+}  // namespace
+}  // namespace mg
+
+using namespace mg;
+
+extern "C" {
+
+int serve_layout(int64_t m, int64_t n, int64_t k, int dtype, int64_t *lda, int64_t *ldb,
+                 int64_t *ldc, int64_t *arena_bytes)
+{
+    if (m <= 0) return -1;
+    if (n <= 0) return -2;
+    if (k <= 0) return -3;
+    if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -4;
+    const int es = in_bytes(dtype);
+    const int64_t q = 16 / es;
+    const int64_t a = round_up(k, q), b = round_up(n, q);
+    if (lda) *lda = a;
+    if (ldb) *ldb = b;
+    if (ldc) *ldc = n;
+    if (arena_bytes)
+        *arena_bytes = round_up(m * a * es, kAlign) + round_up(k * b * es, kAlign) +
+                       round_up(m * n * 4, kAlign);
+    return GEMM_OK;
+}
+
+int serve_run(const serve_config *cfg, int64_t count, const serve_request *reqs,
+              serve_stats *stats, serve_outcome *outcomes)
+{
+    if (check_config(cfg)) return -1;
+    int v = check_requests(count, reqs, true);
+    if (v) return v;
+    ensure_registered();
+    DevState *d = nullptr;
+    int rc = device_state(&d);
+    if (rc != GEMM_OK) return rc;
+    rc = grouped_device_init(d);
+    if (rc != GEMM_OK) return rc;
+    HipBackend be;
+    return run(be, *cfg, count, reqs, stats, outcomes);
+}
+
+int serve_run_sim(const serve_config *cfg, int64_t count, const serve_request *reqs,
+                  const serve_sim *sim, serve_stats *stats, serve_outcome *outcomes)
+{
+    if (check_config(cfg)) return -1;
+    int v = check_requests(count, reqs, false);
+    if (v) return v;
+    if (!sim || !(sim->flops_per_s > 0) || !(sim->bytes_per_s > 0) || sim->launch_overhead_s < 0)
+        return -4;
+    SimBackend be(*sim);
+    return run(be, *cfg, count, reqs, stats, outcomes);
+}
+
+}  // extern "C"

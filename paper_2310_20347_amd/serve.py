@@ -1,0 +1,116 @@
+"""ctypes binding of the serving loop (include/mgemm_serve.h): marshalling only."""
+from __future__ import annotations
+
+import ctypes
+from typing import Any, Optional, Sequence
+
+from ._binding import GEMM_NUM_DTYPES, _check, lib
+
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+_P = ctypes.c_void_p
+_INT = ctypes.c_int
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("arrival_s", _D), ("m", _I64), ("n", _I64), ("k", _I64), ("dtype", _INT),
+                ("a_src", _P), ("b_src", _P), ("result", _P)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("budget_bytes", _I64), ("max_active", _INT), ("step_tile_budget", _I64),
+                ("request_tile_cap", _I64), ("inflight_steps", _INT), ("watchdog_s", _D),
+                ("warmup_requests", _I64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("completed", _I64), ("failed", _I64), ("rejected", _I64), ("measured", _I64),
+                ("window_s", _D), ("req_per_s", _D), ("tflops", _D), ("p50_ms", _D),
+                ("p99_ms", _D), ("mean_ms", _D), ("max_ms", _D),
+                ("count_by_dtype", _I64 * GEMM_NUM_DTYPES),
+                ("p50_ms_by_dtype", _D * GEMM_NUM_DTYPES),
+                ("p99_ms_by_dtype", _D * GEMM_NUM_DTYPES), ("steps", _I64), ("launches", _I64),
+                ("peak_arena_bytes", _I64), ("peak_active", _I64),
+                ("mean_requests_per_launch", _D)]
+
+    def as_dict(self):
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if hasattr(v, "__len__") else v
+        return out
+
+
+class Outcome(ctypes.Structure):
+    _fields_ = [("admit_s", _D), ("done_s", _D), ("latency_ms", _D), ("status", _INT)]
+
+
+class Sim(ctypes.Structure):
+    _fields_ = [("launch_overhead_s", _D), ("flops_per_s", _D), ("bytes_per_s", _D),
+                ("fail_launch", _I64), ("hang_launch", _I64)]
+
+
+_ready = False
+
+
+def _setup():
+    global _ready
+    L = lib()
+    if not _ready:
+        L.serve_layout.argtypes = [_I64, _I64, _I64, _INT, ctypes.POINTER(_I64),
+                                   ctypes.POINTER(_I64), ctypes.POINTER(_I64),
+                                   ctypes.POINTER(_I64)]
+        L.serve_layout.restype = _INT
+        L.serve_run.argtypes = [ctypes.POINTER(Config), _I64, ctypes.POINTER(Request),
+                                ctypes.POINTER(Stats), ctypes.POINTER(Outcome)]
+        L.serve_run.restype = _INT
+        L.serve_run_sim.argtypes = [ctypes.POINTER(Config), _I64, ctypes.POINTER(Request),
+                                    ctypes.POINTER(Sim), ctypes.POINTER(Stats),
+                                    ctypes.POINTER(Outcome)]
+        L.serve_run_sim.restype = _INT
+        _ready = True
+    return L
+
+
+def serve_layout(m: int, n: int, k: int, dtype: int):
+    """(lda, ldb, ldc, arena_bytes) of a request."""
+    out = [_I64() for _ in range(4)]
+    _check(_setup().serve_layout(m, n, k, dtype, *[ctypes.byref(o) for o in out]),
+           "serve_layout")
+    return tuple(int(o.value) for o in out)
+
+
+def config(budget_bytes=64 << 30, max_active=512, step_tile_budget=4096, request_tile_cap=512,
+           inflight_steps=2, watchdog_s=10.0, warmup_requests=0) -> Config:
+    return Config(budget_bytes, max_active, step_tile_budget, request_tile_cap, inflight_steps,
+                  watchdog_s, warmup_requests)
+
+
+def _requests(reqs: Sequence[Any]):
+    arr = (Request * max(1, len(reqs)))()
+    for i, r in enumerate(reqs):
+        arr[i] = r if isinstance(r, Request) else Request(*r)
+    return arr
+
+
+def serve_run(cfg: Config, reqs: Sequence[Any], check: bool = True):
+    """Runs the loop on the GPU; returns (rc, Stats, list of Outcome)."""
+    arr = _requests(reqs)
+    st = Stats()
+    oc = (Outcome * max(1, len(reqs)))()
+    rc = _setup().serve_run(ctypes.byref(cfg), len(reqs), arr, ctypes.byref(st), oc)
+    if check:
+        _check(rc, "serve_run")
+    return rc, st, list(oc)[:len(reqs)]
+
+
+def serve_run_sim(cfg: Config, reqs: Sequence[Any], sim: Sim, check: bool = False):
+    """The same scheduler on the simulated device; returns (rc, Stats, outcomes)."""
+    arr = _requests(reqs)
+    st = Stats()
+    oc = (Outcome * max(1, len(reqs)))()
+    rc = _setup().serve_run_sim(ctypes.byref(cfg), len(reqs), arr, ctypes.byref(sim),
+                                ctypes.byref(st), oc)
+    if check:
+        _check(rc, "serve_run_sim")
+    return rc, st, list(oc)[:len(reqs)]
