@@ -120,7 +120,10 @@ void ensure_registered()
     register_split(g_cfgs);
     register_half(g_cfgs);
     register_byte(g_cfgs);
-    register_resident(g_cfgs);
+    register_resident_f32(g_cfgs);
+    register_resident_split(g_cfgs);
+    register_resident_half(g_cfgs);
+    register_resident_byte(g_cfgs);
     for (size_t i = 0; i < g_cfgs.size(); ++i) g_by_class[g_cfgs[i].kclass].push_back((int)i);
     g_registered = true;
 }
@@ -188,6 +191,8 @@ static bool parse_entry(const std::string &obj, TuneKey &key, TuneVal &val)
     return key.kclass >= 0 && key.kclass < K_NUM && key.trans >= 0 && key.trans < 4;
 }
 
+static void rebuild_lut_locked();
+
 int load_table(const char *path)
 {
     std::ifstream f(path);
@@ -214,6 +219,7 @@ int load_table(const char *path)
     }
     std::lock_guard<std::mutex> g(g_mu);
     g_table = table;
+    rebuild_lut_locked();
     return GEMM_OK;
 }
 
@@ -237,6 +243,47 @@ int save_table(const char *path)
     }
     f << "]}\n";
     return f.good() ? GEMM_OK : GEMM_E_TUNE_TABLE;
+}
+
+// Lookup table resolved from the tuning table for every (class, trans, size
+// bucket): the nearest tuned bucket (L1 distance in log2 buckets, at most 3,
+// an entry of another transposition counting half a step more), or cfg -1
+// when none is near (the heuristic decides).
+static std::vector<TuneVal> g_lut;
+constexpr int kNB = 9;   // buckets 4..12
+static size_t lut_index(int kclass, int trans, int bm, int bn, int bk)
+{
+    return ((((size_t)kclass * 4 + trans) * kNB + (bm - 4)) * kNB + (bn - 4)) * kNB + (bk - 4);
+}
+
+static void rebuild_lut_locked()
+{
+    g_lut.assign((size_t)K_NUM * 4 * kNB * kNB * kNB, TuneVal{-1, 0, 8, 0.0});
+    for (int kc = 0; kc < K_NUM; ++kc)
+        for (int tr = 0; tr < 4; ++tr)
+            for (int bm = 4; bm <= 12; ++bm)
+                for (int bn = 4; bn <= 12; ++bn)
+                    for (int bk = 4; bk <= 12; ++bk) {
+                        double best = 1e9;
+                        TuneVal v{-1, 0, 8, 0.0};
+                        for (auto &kv : g_table) {
+                            const TuneKey &t = kv.first;
+                            if (t.kclass != kc) continue;
+                            const double d = std::abs(t.bm - bm) + std::abs(t.bn - bn) +
+                                             std::abs(t.bk - bk) + (t.trans == tr ? 0.0 : 0.5);
+                            if (d < best) {
+                                best = d;
+                                v = kv.second;
+                            }
+                        }
+                        if (best <= 3.5) g_lut[lut_index(kc, tr, bm, bn, bk)] = v;
+                    }
+}
+
+void rebuild_lut()
+{
+    std::lock_guard<std::mutex> g(g_mu);
+    rebuild_lut_locked();
 }
 
 static void ensure_table()
@@ -288,12 +335,14 @@ void select_config(int kclass, int trans, int64_t m, int64_t n, int64_t k, int c
     ensure_table();
     {
         std::lock_guard<std::mutex> g(g_mu);
-        auto it = g_table.find(TuneKey{kclass, trans, bucket(m), bucket(n), bucket(k)});
-        if (it != g_table.end()) {
-            id = it->second.cfg;
-            order = it->second.order;
-            group = it->second.group;
-            return;
+        if (!g_lut.empty()) {
+            const TuneVal &v = g_lut[lut_index(kclass, trans, bucket(m), bucket(n), bucket(k))];
+            if (v.cfg >= 0 && v.cfg < (int)g_by_class[kclass].size()) {
+                id = v.cfg;
+                order = v.order;
+                group = v.group;
+                return;
+            }
         }
     }
     heuristic(kclass, m, n, cus, id, order, group);

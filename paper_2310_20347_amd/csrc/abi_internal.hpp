@@ -66,6 +66,7 @@ void ensure_registered();
 int device_state(DevState **out);
 int load_table(const char *path);
 int save_table(const char *path);
+void rebuild_lut();
 void select_config(int kclass, int trans, int64_t m, int64_t n, int64_t k, int cus, int &id,
                    int &order, int &group);
 bool vec_ok(const void *X, int64_t ld, int es);

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "registry.hpp"
+#include "resident.hpp"
 #include "tile.hpp"
 
 namespace mg {
@@ -41,6 +42,48 @@ static void add_cfg(std::vector<KernelCfg> &out, int kclass)
         fill_one<DT, MC, NC, WM, WN, ST, true, true, false>(c);
     }
     out.push_back(c);
+}
+
+// Adds an A/B-resident family member (kind 1..4, see resident.hpp); only
+// the vectorised staging variant is compiled (unaligned operands fall back to
+// the class's C-resident configuration 0).
+template <class DT, int MC, int NC, int KIND, bool TA, bool TB>
+static void fill_resident(KernelCfg &c)
+{
+    typedef ResidentTile<DT, MC, NC, KIND, TA, TB, true> T;
+    c.func[2 * TA + TB][1] = (const void *)&gemm_resident_kernel<T>;
+}
+
+template <class DT, int MC, int NC, int KIND>
+static void add_resident(std::vector<KernelCfg> &out, int kclass)
+{
+    typedef ResidentTile<DT, MC, NC, KIND, false, false, true> T;
+    KernelCfg c;
+    c.kclass = kclass;
+    c.mc = MC;
+    c.nc = NC;
+    c.kc = T::KC;
+    const bool ar = (KIND == 1 || KIND == 4);
+    c.wm = ar ? 4 : 1;   // A resident: each wave owns mc/4 rows and walks all nc columns
+    c.wn = ar ? 1 : 4;
+    c.threads = T::NT;
+    c.lds = T::LDS_BYTES;
+    c.stages = 1;
+    c.kind = KIND;
+    fill_resident<DT, MC, NC, KIND, false, false>(c);
+    fill_resident<DT, MC, NC, KIND, false, true>(c);
+    fill_resident<DT, MC, NC, KIND, true, false>(c);
+    fill_resident<DT, MC, NC, KIND, true, true>(c);
+    out.push_back(c);
+}
+
+template <class DT>
+static void add_resident_family(std::vector<KernelCfg> &out, int kclass)
+{
+    add_resident<DT, 64, 64, 1>(out, kclass);   // B3C2A0
+    add_resident<DT, 64, 64, 2>(out, kclass);   // A3C2B0
+    add_resident<DT, 64, 64, 3>(out, kclass);   // C3A2B0
+    add_resident<DT, 64, 64, 4>(out, kclass);   // C3B2A0
 }
 
 }  // namespace mg

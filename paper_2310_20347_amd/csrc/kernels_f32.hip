@@ -9,5 +9,6 @@ void register_f32(std::vector<KernelCfg> &out)
     add_cfg<TF32, 128, 128, 2, 2, 2, false>(out, K_F32);
     add_cfg<TF32, 128, 64, 2, 2, 2, false>(out, K_F32);
     add_cfg<TF32, 256, 128, 2, 2, 2, false>(out, K_F32);
+    add_cfg<TF32, 256, 256, 2, 2, 2, false>(out, K_F32);
 }
 }  // namespace mg

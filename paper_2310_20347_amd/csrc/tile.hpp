@@ -253,45 +253,45 @@ struct Stage {
 };
 
 // ---------------------------------------------------------------------------
-// One fragment chunk of the micro-kernel: acc += a * b over KF values of k.
-// A lane of group g = lane/16 holds the k values g*KF/4 .. g*KF/4 + KF/4-1 of
+// One MFMA of the micro-kernel.  A fragment chunk covers KF values of k: a
+// lane of group g = lane/16 holds the k values g*KF/4 .. g*KF/4 + KF/4-1 of
 // its row (A) or column (B); A and B use the same k assignment, so every k of
-// the chunk is summed exactly once.
+// the chunk is summed exactly once.  A chunk takes SUB MFMAs per 16x16 block:
+// the four k=4 steps of the FP32 instruction, or the piece products of the
+// split path, or one instruction otherwise.  Sub-step s of every block is
+// issued before sub-step s+1 of any block, so consecutive MFMAs write
+// different accumulators; each block still sums its sub-steps in order.
 // ---------------------------------------------------------------------------
 template <class DT>
-__device__ __forceinline__ void mma(typename AccOf<DT>::type &acc, const u32 (*a)[DT::FDW],
-                                    const u32 (*b)[DT::FDW])
+struct Sub {
+    static constexpr int value = DT::SPLIT ? (DT::PLANES == 2 ? 3 : 6) : (DT::GES == 4 ? 4 : 1);
+};
+
+template <class DT>
+__device__ __forceinline__ void mma_step(typename AccOf<DT>::type &acc, const u32 (*a)[DT::FDW],
+                                         const u32 (*b)[DT::FDW], int s)
 {
     if constexpr (DT::SPLIT) {
         // piece products, smallest first; planes: 0 = hi, 1 = mid, 2 = lo
+        // three terms: mid*hi, hi*mid, hi*hi; six terms: lo*hi, hi*lo, mid*mid, then those
         constexpr int P = DT::PLANES;
-        constexpr int NT = (P == 2) ? 3 : 6;
-        constexpr int TU[6] = {P == 2 ? 1 : 2, P == 2 ? 0 : 0, P == 2 ? 0 : 1, 1, 0, 0};
-        constexpr int TV[6] = {P == 2 ? 0 : 0, P == 2 ? 1 : 2, P == 2 ? 0 : 1, 0, 1, 0};
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const u32 *x = a[TU[t]], *y = b[TV[t]];
-            u32x4 xv = {x[0], x[1], x[2], x[3]}, yv = {y[0], y[1], y[2], y[3]};
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, xv),
-                                                          __builtin_bit_cast(bf16x8, yv), acc,
-                                                          0, 0, 0);
-        }
-    } else if constexpr (DT::GES == 4) {  // plain FP32: four k=4 MFMAs
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__builtin_bit_cast(float, a[0][s]),
-                                                      __builtin_bit_cast(float, b[0][s]), acc,
-                                                      0, 0, 0);
+        constexpr int TU[6] = {P == 2 ? 1 : 2, 0, P == 2 ? 0 : 1, 1, 0, 0};
+        constexpr int TV[6] = {0, P == 2 ? 1 : 2, P == 2 ? 0 : 1, 0, 1, 0};
+        const u32 *x = a[TU[s]], *y = b[TV[s]];
+        u32x4 xv = {x[0], x[1], x[2], x[3]}, yv = {y[0], y[1], y[2], y[3]};
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, xv),
+                                                      __builtin_bit_cast(bf16x8, yv), acc, 0, 0, 0);
+    } else if constexpr (DT::GES == 4) {  // plain FP32: k step s of four
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__builtin_bit_cast(float, a[0][s]),
+                                                  __builtin_bit_cast(float, b[0][s]), acc, 0, 0, 0);
     } else if constexpr (DT::GES == 2) {
         u32x4 xv = {a[0][0], a[0][1], a[0][2], a[0][3]}, yv = {b[0][0], b[0][1], b[0][2], b[0][3]};
         if constexpr (DT::HALF)
             acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, xv),
-                                                         __builtin_bit_cast(f16x8, yv), acc, 0,
-                                                         0, 0);
+                                                         __builtin_bit_cast(f16x8, yv), acc, 0, 0, 0);
         else
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, xv),
-                                                          __builtin_bit_cast(bf16x8, yv), acc,
-                                                          0, 0, 0);
+                                                          __builtin_bit_cast(bf16x8, yv), acc, 0, 0, 0);
     } else if constexpr (DT::INT) {
         i32x4 xv = {(int)a[0][0], (int)a[0][1], (int)a[0][2], (int)a[0][3]};
         i32x4 yv = {(int)b[0][0], (int)b[0][1], (int)b[0][2], (int)b[0][3]};
@@ -361,9 +361,11 @@ struct Tile {
             for (int j = 0; j < FN; ++j)
                 read_frag<DT>(pb, PLANE_B, wn * WTN + 16 * j, c, lane, fb[j]);
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
+            for (int st = 0; st < Sub<DT>::value; ++st)
 #pragma unroll
-                for (int j = 0; j < FN; ++j) mma<DT>(acc[i][j], fa[i], fb[j]);
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) mma_step<DT>(acc[i][j], fa[i], fb[j], st);
         }
     }
 

@@ -148,6 +148,7 @@ extern "C" int gemm_tune(int dtype, int64_t count, const int64_t *shapes, int re
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipStreamDestroy(s);
+    rebuild_lut();
     if (out_path && *out_path) return save_table(out_path);
     return GEMM_OK;
 }
