@@ -54,11 +54,11 @@ struct TF32 {
     static constexpr bool INT = false, SPLIT = false;
 };
 struct TBF16 {
-    static constexpr int GES = 2, LES = 2, PLANES = 1, FDW = 4, KF = 32, MNV = 8;
+    static constexpr int GES = 2, LES = 2, PLANES = 1, FDW = 4, KF = 32, MNV = 4;
     static constexpr bool INT = false, SPLIT = false, HALF = false;
 };
 struct TF16 {
-    static constexpr int GES = 2, LES = 2, PLANES = 1, FDW = 4, KF = 32, MNV = 8;
+    static constexpr int GES = 2, LES = 2, PLANES = 1, FDW = 4, KF = 32, MNV = 4;
     static constexpr bool INT = false, SPLIT = false, HALF = true;
 };
 struct TI8 {

@@ -178,11 +178,12 @@ struct ResidentTile {
         constexpr bool RKMODE = AR ? !TA : TB;   // resident operand contiguous along k
 
         StageP sp;
-        if (nk > 0) sp.load(Pm, pld, prow0, pR, 0, p.k, tid);
+        const bool fullP = prow0 + PROWS <= pR;
+        if (nk > 0) sp.load_any(fullP, Pm, pld, prow0, pR, 0, p.k, tid);
         for (int s = 0; s < nk; ++s) {
             sp.store(pk, PLANE, tid);
             __syncthreads();
-            if (s + 1 < nk) sp.load(Pm, pld, prow0, pR, (s + 1) * KC, p.k, tid);
+            if (s + 1 < nk) sp.load_any(fullP, Pm, pld, prow0, pR, (s + 1) * KC, p.k, tid);
 #pragma unroll
             for (int c = 0; c < KC / DT::KF; ++c) {
                 u32 res[RB][DT::PLANES][DT::FDW];

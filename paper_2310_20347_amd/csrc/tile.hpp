@@ -108,6 +108,56 @@ struct Stage {
 
     u32 reg[PER][DW];
 
+    // A full interior stage (all ROWS rows and all KC columns of the stage in
+    // bounds, vectorisable operand): plain vector loads, no checks, no
+    // branches, so the loads can be scheduled among the MFMAs.
+    __device__ __forceinline__ void load_fast(const char *X, int64_t ld, int row0, int k0,
+                                              int tid)
+    {
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const int item = tid + it * NT;
+            if (ITEMS % NT != 0 && item >= ITEMS) break;
+            if constexpr (KMODE) {
+                const int row = item / VPR, kv = item % VPR;
+                const u32x4 v =
+                    *(const u32x4 *)(X + ((int64_t)(row0 + row) * ld + k0 + kv * VK) * GES);
+#pragma unroll
+                for (int d = 0; d < 4; ++d) reg[it][d] = v[d];
+            } else {
+                const int mb = item % MB, kb = item / MB;
+                const char *p = X + ((int64_t)(k0 + kb * KV) * ld + row0 + mb * MNV) * GES;
+                const int64_t step = ld * GES;
+#pragma unroll
+                for (int r = 0; r < KV; ++r) {
+                    const char *q = p + r * step;
+                    if constexpr (GVB == 16) {
+                        const u32x4 v = *(const u32x4 *)q;
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) reg[it][r * 4 + d] = v[d];
+                    } else if constexpr (GVB == 8) {
+                        const u32x2 v = *(const u32x2 *)q;
+                        reg[it][r * 2 + 0] = v[0];
+                        reg[it][r * 2 + 1] = v[1];
+                    } else {
+                        reg[it][r] = *(const u32 *)q;
+                    }
+                }
+            }
+        }
+    }
+
+    // Stage starting at k0: the fast path when `full` (rows and k in bounds)
+    // and the operand is vectorisable, the checked path otherwise.
+    __device__ __forceinline__ void load_any(bool full, const char *X, int64_t ld, int row0, int R,
+                                             int k0, int K, int tid)
+    {
+        if (VEC && full && k0 + KC <= K)
+            load_fast(X, ld, row0, k0, tid);
+        else
+            load(X, ld, row0, R, k0, K, tid);
+    }
+
     // Load stage starting at k0 from the operand X (row stride ld elements),
     // whose panel starts at row0; R rows and K columns are valid.
     __device__ __forceinline__ void load(const char *X, int64_t ld, int row0, int R, int k0,
@@ -142,6 +192,10 @@ struct Stage {
                         if (VEC && gmn + MNV <= R) {
                             if constexpr (GVB == 16) {
                                 v = *(const u32x4 *)p;
+                            } else if constexpr (GVB == 8) {
+                                const u32x2 w = *(const u32x2 *)p;
+                                v[0] = w[0];
+                                v[1] = w[1];
                             } else {
                                 v[0] = *(const u32 *)p;
                             }
@@ -221,13 +275,13 @@ struct Stage {
                                    reg[it][3 * 4 + e]};
                         *(u32x4 *)(planes + lds_off<MNV>(row, kb * 16)) = w;
                     } else if constexpr (GES == 2) {
-                        // 8 k-rows x 8 halves: half e of each row, paired into dwords
+                        // 8 k-rows x MNV halves: half e of each row, paired into dwords
                         const int d = e / 2, sh = 16 * (e % 2);
                         u32 w4[4];
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
-                            const u32 lo = (reg[it][(2 * q) * 4 + d] >> sh) & 0xFFFFu;
-                            const u32 hi = (reg[it][(2 * q + 1) * 4 + d] >> sh) & 0xFFFFu;
+                            const u32 lo = (reg[it][(2 * q) * (GVB / 4) + d] >> sh) & 0xFFFFu;
+                            const u32 hi = (reg[it][(2 * q + 1) * (GVB / 4) + d] >> sh) & 0xFFFFu;
                             w4[q] = lo | (hi << 16);
                         }
                         u32x4 w = {w4[0], w4[1], w4[2], w4[3]};
@@ -389,9 +443,10 @@ struct Tile {
 
         StageA sa;
         StageB sb;
+        const bool fullA = m0 + MC <= p.m, fullB = n0 + NC <= p.n;   // panel rows in bounds
         if (nk > 0) {
-            sa.load(A, p.lda, m0, p.m, 0, p.k, tid);
-            sb.load(B, p.ldb, n0, p.n, 0, p.k, tid);
+            sa.load_any(fullA, A, p.lda, m0, p.m, 0, p.k, tid);
+            sb.load_any(fullB, B, p.ldb, n0, p.n, 0, p.k, tid);
         }
         if constexpr (STAGES == 2) {
             if (nk > 0) {
@@ -403,8 +458,8 @@ struct Tile {
                 char *cur = lds + (s & 1) * STAGE_BYTES;
                 char *nxt = lds + ((s + 1) & 1) * STAGE_BYTES;
                 if (s + 1 < nk) {
-                    sa.load(A, p.lda, m0, p.m, (s + 1) * KC, p.k, tid);
-                    sb.load(B, p.ldb, n0, p.n, (s + 1) * KC, p.k, tid);
+                    sa.load_any(fullA, A, p.lda, m0, p.m, (s + 1) * KC, p.k, tid);
+                    sb.load_any(fullB, B, p.ldb, n0, p.n, (s + 1) * KC, p.k, tid);
                 }
                 compute(cur, acc, wm, wn, lane);
                 if (s + 1 < nk) {
@@ -419,8 +474,8 @@ struct Tile {
                 sb.store(lds + DT::PLANES * PLANE_A, PLANE_B, tid);
                 __syncthreads();
                 if (s + 1 < nk) {
-                    sa.load(A, p.lda, m0, p.m, (s + 1) * KC, p.k, tid);
-                    sb.load(B, p.ldb, n0, p.n, (s + 1) * KC, p.k, tid);
+                    sa.load_any(fullA, A, p.lda, m0, p.m, (s + 1) * KC, p.k, tid);
+                    sb.load_any(fullB, B, p.ldb, n0, p.n, (s + 1) * KC, p.k, tid);
                 }
                 compute(lds, acc, wm, wn, lane);
                 __syncthreads();
