@@ -134,7 +134,12 @@ int64_t gemm_grouped_capacity(void);
  *   gemm_grouped_slot_write(slot, count, problems, dtype): validates like
  *     gemm_grouped (errors -(1000*p + i)) and writes the table into the slot's
  *     pinned memory.  The dtype family (FP32 / split / BF16 / FP16 / FP8 /
- *     INT8) of a slot is fixed by its first write.  count <= capacity.
+ *     INT8) of a slot is fixed by its first write, and so is its kernel: a
+ *     first batch whose problems are all 'N','N' with 16-byte aligned A, B
+ *     and leading dimensions selects the compact kernel for that case, and
+ *     later batches that do not qualify return GEMM_E_UNSUPPORTED (any
+ *     other first batch selects the general kernel, which takes anything).
+ *     count <= capacity.
  *   gemm_grouped_slot_launch(slot): enqueues, on the current stream, one copy
  *     of the pinned table (header + capacity descriptors) to the device and
  *     one persistent kernel launch whose grid does not depend on the table.

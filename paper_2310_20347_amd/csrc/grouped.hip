@@ -47,13 +47,14 @@ struct Slot {
     hipEvent_t done = nullptr;
     bool used = false;
     int family = -1;
+    int variant = -1;   // kernel variant fixed by the first write (0 full, 1 lean)
     int device = 0;
     int64_t capacity = kCapacity;
 };
 
 struct GroupedDev {
     GroupedFamily fam[G_NUM];
-    int grid[G_NUM] = {0, 0, 0, 0, 0, 0};
+    int grid[G_NUM][2] = {};   // [family][0 full, 1 lean]
     Slot rot[kRotating];
     int next = 0;
     std::mutex mu;
@@ -106,10 +107,13 @@ int grouped_device_init(DevState *d)
     GroupedDev *gd = new GroupedDev();
     for (int f = 0; f < G_NUM; ++f) {
         gd->fam[f] = grouped_family(f);
-        int per_cu = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gd->fam[f].func, 256, 0);
-        if (e != hipSuccess || per_cu < 1) per_cu = 1;
-        gd->grid[f] = d->cus * per_cu;
+        for (int v = 0; v < 2; ++v) {
+            int per_cu = 0;
+            const void *fn = v ? gd->fam[f].lean : gd->fam[f].func;
+            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0);
+            if (e != hipSuccess || per_cu < 1) per_cu = 1;
+            gd->grid[f][v] = d->cus * per_cu;
+        }
     }
     for (int i = 0; i < kRotating; ++i) {
         int rc = slot_alloc(gd->rot[i], d->device);
@@ -151,9 +155,12 @@ static int ensure_grouped(DevState **out)
 }
 
 // Builds the descriptor table of `count` problems into `table` (host memory).
-// Returns 0 / -(1000*p + i) / GEMM_E_*; sets total tiles in the header.
+// `want`: -1 choose, 0 full kernel, 1 lean kernel.  The lean kernel serves
+// batches whose problems are all 'N','N' with vectorisable operands; *variant
+// receives the kernel the table was built for.  Returns 0 / -(1000*p + i) /
+// GEMM_E_*; sets total tiles in the header.
 static int build_table(const GroupedDev *gd, int cus, int64_t count, const gemm_problem *pr,
-                       int dtype, char *table)
+                       int dtype, char *table, int want, int *variant)
 {
     if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -3;
     if (count < 0) return -1;
@@ -168,6 +175,15 @@ static int build_table(const GroupedDev *gd, int cus, int64_t count, const gemm_
         if (v != 0) return (int)(-1000 * p + v);
         if (q.m > 0x7FFFFFFF || q.n > 0x7FFFFFFF || q.k > 0x7FFFFFFF) return GEMM_E_UNSUPPORTED;
     }
+    bool lean = want != 0;
+    for (int64_t p = 0; p < count && lean; ++p) {
+        const gemm_problem &q = pr[p];
+        const bool nn = (q.transA == 'N' || q.transA == 'n') && (q.transB == 'N' || q.transB == 'n');
+        const int es = elem_bytes(kclass_of(dtype, q.k));
+        lean = nn && vec_ok(q.A, q.lda, es) && vec_ok(q.B, q.ldb, es);
+    }
+    if (want == 1 && !lean) return GEMM_E_UNSUPPORTED;
+    *variant = lean ? 1 : 0;
     GHeader *h = (GHeader *)table;
     GDesc *descs = (GDesc *)(table + sizeof(GHeader));
     std::vector<GDesc> tmp;
@@ -183,14 +199,22 @@ static int build_table(const GroupedDev *gd, int cus, int64_t count, const gemm_
         const int kclass = kclass_of(dtype, q.k);
         int cfg = 0, order = 0, group = 8;
         select_config(kclass, trans, q.m, q.n, q.k, cus, cfg, order, group);
-        int shape;
-        if (kclass == K_SPLIT3)
-            shape = 2;
-        else
-            shape = (cfg == 0 || q.m < F.mc[1] || q.n < F.nc[1]) ? 0 : 1;
+        int shape, mc, nc;
         const int es = elem_bytes(kclass);
         const bool vec = vec_ok(q.A, q.lda, es) && vec_ok(q.B, q.ldb, es);
-        if (!vec && shape == 1) shape = 0;
+        if (lean) {
+            shape = kclass == K_SPLIT3 ? 1 : 0;
+            mc = F.lean_mc[shape];
+            nc = F.lean_nc[shape];
+        } else {
+            if (kclass == K_SPLIT3)
+                shape = 2;
+            else
+                shape = (cfg == 0 || q.m < F.mc[1] || q.n < F.nc[1]) ? 0 : 1;
+            if (!vec && shape == 1) shape = 0;
+            mc = F.mc[shape];
+            nc = F.nc[shape];
+        }
         GDesc d;
         std::memset(&d, 0, sizeof d);
         GemmArgs &a = d.a;
@@ -207,16 +231,16 @@ static int build_table(const GroupedDev *gd, int cus, int64_t count, const gemm_
         a.beta = (float)q.beta;
         a.ialpha = dtype == GEMM_I8 ? (int)q.alpha : 0;
         a.ibeta = dtype == GEMM_I8 ? (int)q.beta : 0;
-        a.tiles_m = (int)((q.m + F.mc[shape] - 1) / F.mc[shape]);
-        a.tiles_n = (int)((q.n + F.nc[shape] - 1) / F.nc[shape]);
+        a.tiles_m = (int)((q.m + mc - 1) / mc);
+        a.tiles_n = (int)((q.n + nc - 1) / nc);
         a.order = order;
         a.group = std::max(1, group);
         a.terms = split_terms(kclass);
-        d.body = shape * 8 + trans * 2 + (vec ? 1 : 0);
+        d.body = lean ? shape : shape * 8 + trans * 2 + (vec ? 1 : 0);
         tmp.push_back(d);
         // per-tile work: the k loop length times the tile area
         const double kk = (q.alpha == 0.0) ? 0.0 : double(q.k);
-        cost.push_back((kk + 64.0) * F.mc[shape] * F.nc[shape]);
+        cost.push_back((kk + 64.0) * mc * nc);
     }
     std::vector<size_t> idx(tmp.size());
     std::iota(idx.begin(), idx.end(), 0);
@@ -236,8 +260,8 @@ static int build_table(const GroupedDev *gd, int cus, int64_t count, const gemm_
     return GEMM_OK;
 }
 
-static int launch_table(const GroupedDev *gd, const Slot &s, int fam, int grid, size_t bytes,
-                        hipStream_t st)
+static int launch_table(const GroupedDev *gd, const Slot &s, int fam, int variant, int grid,
+                        size_t bytes, hipStream_t st)
 {
     hipError_t e = hipMemcpyAsync(s.dev, s.host, bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) {
@@ -247,7 +271,8 @@ static int launch_table(const GroupedDev *gd, const Slot &s, int fam, int grid, 
     const char *table = s.dev;
     int *counters = s.counters;
     void *args[] = {&table, &counters};
-    e = hipLaunchKernel(gd->fam[fam].func, dim3(grid), dim3(256), args, 0, st);
+    e = hipLaunchKernel(variant ? gd->fam[fam].lean : gd->fam[fam].func, dim3(grid), dim3(256),
+                        args, 0, st);
     if (e != hipSuccess) {
         t_tls.hip_err = (int)e;
         return GEMM_E_HIP;
@@ -289,7 +314,8 @@ int gemm_grouped(int64_t count, const gemm_problem *problems, int dtype)
             return GEMM_E_HIP;
         }
     }
-    rc = build_table(gd, d->cus, count, problems, dtype, s.host);
+    int variant = 0;
+    rc = build_table(gd, d->cus, count, problems, dtype, s.host, -1, &variant);
     if (rc != GEMM_OK) return rc;
     const GHeader *h = (const GHeader *)s.host;
     if (h->total_tiles == 0) {
@@ -297,10 +323,10 @@ int gemm_grouped(int64_t count, const gemm_problem *problems, int dtype)
         return GEMM_OK;
     }
     const int fam = family_of(dtype);
-    const int grid = std::min(gd->grid[fam], h->total_tiles);
+    const int grid = std::min(gd->grid[fam][variant], h->total_tiles);
     const size_t bytes = sizeof(GHeader) + size_t(h->count) * sizeof(GDesc);
     hipStream_t st = t_tls.stream;
-    rc = launch_table(gd, s, fam, grid, bytes, st);
+    rc = launch_table(gd, s, fam, variant, grid, bytes, st);
     if (rc != GEMM_OK) return rc;
     hipError_t e = hipEventRecord(s.done, st);
     if (e != hipSuccess) {
@@ -348,7 +374,9 @@ int gemm_grouped_slot_write(void *slot, int64_t count, const gemm_problem *probl
     if (rc != GEMM_OK) return rc;
     // build into a private buffer first so a failed validation leaves the slot intact
     std::vector<char> buf(sizeof(GHeader) + size_t(std::max<int64_t>(count, 0)) * sizeof(GDesc));
-    rc = build_table((GroupedDev *)d->grouped, d->cus, count, problems, dtype, buf.data());
+    int variant = 0;
+    rc = build_table((GroupedDev *)d->grouped, d->cus, count, problems, dtype, buf.data(),
+                     s->variant, &variant);
     if (rc != GEMM_OK) {
         // a problem error is reported as in gemm_grouped: -(1000*p + i)
         return rc;
@@ -356,6 +384,7 @@ int gemm_grouped_slot_write(void *slot, int64_t count, const gemm_problem *probl
     const GHeader *h = (const GHeader *)buf.data();
     std::memcpy(s->host, buf.data(), sizeof(GHeader) + size_t(h->count) * sizeof(GDesc));
     s->family = fam;
+    s->variant = variant;
     return GEMM_OK;
 }
 
@@ -371,7 +400,8 @@ int gemm_grouped_slot_launch(void *slot)
     // the grid does not depend on the table, so a captured launch stays valid
     // when the slot is rewritten; header + capacity descriptors are copied
     const size_t bytes = sizeof(GHeader) + size_t(s->capacity) * sizeof(GDesc);
-    return launch_table(gd, *s, s->family, gd->grid[s->family], bytes, t_tls.stream);
+    return launch_table(gd, *s, s->family, s->variant, gd->grid[s->family][s->variant], bytes,
+                        t_tls.stream);
 }
 
 void gemm_grouped_slot_destroy(void *slot)

@@ -73,10 +73,41 @@ __device__ __forceinline__ void run_body(int body, const GemmArgs &p, int tm, in
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
-template <class S0, class S1, class S2>
-__global__ void __launch_bounds__(256) grouped_kernel(const char *table, int *counters)
+// All bodies: shapes 0..2 x four transpositions x staging variants.
+template <class S0, class S1, class S2, int MINB_>
+struct FullBodies {
+    static constexpr int LDS = cmax(cmax(S0::lds, S1::lds), S2::lds);
+    static constexpr int MINB = MINB_;
+    static __device__ __forceinline__ void run(int body, const GemmArgs &p, int tm, int tn, char *lds)
+    {
+        run_body<S0, S1, S2>(body, p, tm, tn, lds);
+    }
+};
+
+// Lean bodies: 'N','N' operands with vectorised staging only, one shape
+// (plus, for the split family, the six-term shape): a few thousand
+// instructions instead of tens of thousands, so the persistent loop runs from
+// the instruction cache.  Body 0 -> SA, body 1 -> SB.
+template <class SA, class SB, int MINB_>
+struct LeanBodies {
+    static constexpr int LDS = cmax(SA::lds, SB::lds);
+    static constexpr int MINB = MINB_;
+    static __device__ __forceinline__ void run(int body, const GemmArgs &p, int tm, int tn, char *lds)
+    {
+        if constexpr (SB::lds > 0) {
+            if (body == 1) {
+                Tile<typename SB::dt, SB::mc, SB::nc, 2, 2, false, false, true, SB::st>::run(p, tm, tn, lds);
+                return;
+            }
+        }
+        Tile<typename SA::dt, SA::mc, SA::nc, 2, 2, false, false, true, SA::st>::run(p, tm, tn, lds);
+    }
+};
+
+template <class BODIES>
+__global__ void __launch_bounds__(256, BODIES::MINB) grouped_kernel(const char *table, int *counters)
 {
-    __shared__ __attribute__((aligned(16))) char lds[cmax(cmax(S0::lds, S1::lds), S2::lds)];
+    __shared__ __attribute__((aligned(16))) char lds[BODIES::LDS];
     __shared__ int s_next;
     const GHeader *h = (const GHeader *)table;
     const GDesc *descs = (const GDesc *)(table + sizeof(GHeader));
@@ -93,7 +124,7 @@ __global__ void __launch_bounds__(256) grouped_kernel(const char *table, int *co
         const int body = descs[lo].body;
         int tm, tn;
         raster(t - descs[lo].tile_start, p.tiles_m, p.tiles_n, p.order, p.group, tm, tn);
-        run_body<S0, S1, S2>(body, p, tm, tn, lds);
+        BODIES::run(body, p, tm, tn, lds);
         if (threadIdx.x == 0) s_next = (int)gridDim.x + atomicAdd(&counters[0], 1);
         __syncthreads();
         t = __builtin_amdgcn_readfirstlane(s_next);
@@ -108,19 +139,20 @@ __global__ void __launch_bounds__(256) grouped_kernel(const char *table, int *co
     }
 }
 
-// What the host needs to know about one family's kernel.
+// What the host needs to know about one family's kernels.
 struct GroupedFamily {
-    const void *func = nullptr;
+    const void *func = nullptr;       // all bodies
     int nshapes = 0;
     int mc[3] = {0, 0, 0}, nc[3] = {0, 0, 0};
-    int lds = 0;
+    const void *lean = nullptr;       // 'N','N', aligned operands only
+    int lean_mc[2] = {0, 0}, lean_nc[2] = {0, 0};
 };
 
-template <class S0, class S1, class S2>
+template <class S0, class S1, class S2, int MINB, class LA, class LB, int LMINB>
 GroupedFamily make_family()
 {
     GroupedFamily f;
-    f.func = (const void *)&grouped_kernel<S0, S1, S2>;
+    f.func = (const void *)&grouped_kernel<FullBodies<S0, S1, S2, MINB>>;
     f.mc[0] = S0::mc;
     f.nc[0] = S0::nc;
     f.mc[1] = S1::mc;
@@ -131,7 +163,13 @@ GroupedFamily make_family()
         f.nc[2] = S2::nc;
         f.nshapes = 3;
     }
-    f.lds = cmax(cmax(S0::lds, S1::lds), S2::lds);
+    f.lean = (const void *)&grouped_kernel<LeanBodies<LA, LB, LMINB>>;
+    f.lean_mc[0] = LA::mc;
+    f.lean_nc[0] = LA::nc;
+    if constexpr (LB::lds > 0) {
+        f.lean_mc[1] = LB::mc;
+        f.lean_nc[1] = LB::nc;
+    }
     return f;
 }
 

@@ -1,11 +1,13 @@
-// Grouped persistent kernel of the f16 family (see grouped.hpp).  Shape 0 is
-// a 64x64 tile with element-wise variants for unaligned operands, shape 1 a
-// 128x128 tile.
+// Grouped persistent kernels of the f16 family (see grouped.hpp).
+// Full kernel: shape 0 is a 64x64 tile with element-wise variants for
+// unaligned operands, shape 1 a 128x64 tile; all four
+// transpositions.  Lean kernel: one 128x128 'N','N' body.
 #include "grouped.hpp"
 
 namespace mg {
 GroupedFamily grouped_family_f16()
 {
-    return make_family<Shape<TF16, 64, 64, 2>, Shape<TF16, 128, 128, 2>, NoShape>();
+    return make_family<Shape<TF16, 64, 64, 2>, Shape<TF16, 128, 64, 2>, NoShape, 2,
+                       Shape<TF16, 128, 128, 2>, NoShape, 2>();
 }
 }  // namespace mg

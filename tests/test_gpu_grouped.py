@@ -189,3 +189,27 @@ def test_grouped_rejects_bad_problem_and_capacity():
     assert mg.gemm_grouped(bad, mg.GEMM_F32, check=False) == -(1000 * 1 + 8)
     assert mg.lib().gemm_grouped(mg.gemm_grouped_capacity() + 1, None, mg.GEMM_F32) == -2
     torch.cuda.synchronize()
+
+
+def test_slot_keeps_the_kernel_of_its_first_write():
+    """A slot first written with an all-'N','N' aligned batch uses the compact
+    kernel and rejects a later batch it cannot run; the general kernel accepts
+    everything."""
+    import torch
+    dtype = mg.GEMM_BF16
+    mg.gemm_init(None)
+    nn = Batch(dtype, [(64, 64, 64), (130, 70, 90)], seed=51)
+    mixed = Batch(dtype, [(64, 64, 64), (30, 20, 10)], seed=52, trans=[("N", "N"), ("T", "N")])
+    s1, s2 = mg.GroupedSlot(capacity=8), mg.GroupedSlot(capacity=8)
+    try:
+        s1.write(nn.problems, dtype)
+        assert s1.write(mixed.problems, dtype, check=False) == 2      # GEMM_E_UNSUPPORTED
+        s2.write(mixed.problems, dtype)
+        s2.write(nn.problems, dtype)                                  # general kernel: fine
+        s2.launch()
+        torch.cuda.synchronize()
+        for p, h, C in zip(nn.problems, nn.host, nn.results()):
+            oracle_check(dtype, p, h, C)
+    finally:
+        s1.destroy()
+        s2.destroy()
