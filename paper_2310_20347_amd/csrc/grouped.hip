@@ -38,7 +38,9 @@ GroupedFamily grouped_family(int fam)
 
 constexpr int64_t kCapacity = 8192;   // problems per descriptor table
 constexpr int kRotating = 4;          // rotating slots of gemm_grouped per device
-constexpr size_t kTableBytes = sizeof(GHeader) + kCapacity * sizeof(GDesc);
+// header, descriptors, then the compact tile_start array (one int per problem)
+constexpr size_t table_bytes(int64_t cap) { return sizeof(GHeader) + size_t(cap) * (sizeof(GDesc) + 4); }
+constexpr size_t kTableBytes = table_bytes(kCapacity);
 
 struct Slot {
     char *host = nullptr;     // pinned staging
@@ -160,7 +162,7 @@ static int ensure_grouped(DevState **out)
 // receives the kernel the table was built for.  Returns 0 / -(1000*p + i) /
 // GEMM_E_*; sets total tiles in the header.
 static int build_table(const GroupedDev *gd, int cus, int64_t count, const gemm_problem *pr,
-                       int dtype, char *table, int want, int *variant)
+                       int dtype, char *table, int want, int *variant, int64_t cap)
 {
     if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -3;
     if (count < 0) return -1;
@@ -245,10 +247,13 @@ static int build_table(const GroupedDev *gd, int cus, int64_t count, const gemm_
     std::vector<size_t> idx(tmp.size());
     std::iota(idx.begin(), idx.end(), 0);
     std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+    if (cap <= 0) cap = (int64_t)idx.size();
+    int *ts = (int *)(table + sizeof(GHeader) + size_t(cap) * sizeof(GDesc));
     int64_t tiles = 0;
     for (size_t i = 0; i < idx.size(); ++i) {
         GDesc d = tmp[idx[i]];
         d.tile_start = (int)tiles;
+        ts[i] = (int)tiles;
         tiles += int64_t(d.a.tiles_m) * d.a.tiles_n;
         if (tiles > 0x7FFFFFFF) return GEMM_E_UNSUPPORTED;
         descs[i] = d;
@@ -257,6 +262,7 @@ static int build_table(const GroupedDev *gd, int cus, int64_t count, const gemm_
     h->count = (int)idx.size();
     h->total_tiles = (int)tiles;
     h->family = fam;
+    h->ts_offset = (int)(sizeof(GHeader) + size_t(cap) * sizeof(GDesc));
     return GEMM_OK;
 }
 
@@ -315,7 +321,7 @@ int gemm_grouped(int64_t count, const gemm_problem *problems, int dtype)
         }
     }
     int variant = 0;
-    rc = build_table(gd, d->cus, count, problems, dtype, s.host, -1, &variant);
+    rc = build_table(gd, d->cus, count, problems, dtype, s.host, -1, &variant, 0);
     if (rc != GEMM_OK) return rc;
     const GHeader *h = (const GHeader *)s.host;
     if (h->total_tiles == 0) {
@@ -324,7 +330,7 @@ int gemm_grouped(int64_t count, const gemm_problem *problems, int dtype)
     }
     const int fam = family_of(dtype);
     const int grid = std::min(gd->grid[fam][variant], h->total_tiles);
-    const size_t bytes = sizeof(GHeader) + size_t(h->count) * sizeof(GDesc);
+    const size_t bytes = table_bytes(h->count);
     hipStream_t st = t_tls.stream;
     rc = launch_table(gd, s, fam, variant, grid, bytes, st);
     if (rc != GEMM_OK) return rc;
@@ -373,16 +379,15 @@ int gemm_grouped_slot_write(void *slot, int64_t count, const gemm_problem *probl
     int rc = ensure_grouped(&d);
     if (rc != GEMM_OK) return rc;
     // build into a private buffer first so a failed validation leaves the slot intact
-    std::vector<char> buf(sizeof(GHeader) + size_t(std::max<int64_t>(count, 0)) * sizeof(GDesc));
+    std::vector<char> buf(table_bytes(s->capacity));
     int variant = 0;
     rc = build_table((GroupedDev *)d->grouped, d->cus, count, problems, dtype, buf.data(),
-                     s->variant, &variant);
+                     s->variant, &variant, s->capacity);
     if (rc != GEMM_OK) {
         // a problem error is reported as in gemm_grouped: -(1000*p + i)
         return rc;
     }
-    const GHeader *h = (const GHeader *)buf.data();
-    std::memcpy(s->host, buf.data(), sizeof(GHeader) + size_t(h->count) * sizeof(GDesc));
+    std::memcpy(s->host, buf.data(), table_bytes(s->capacity));
     s->family = fam;
     s->variant = variant;
     return GEMM_OK;
@@ -399,7 +404,7 @@ int gemm_grouped_slot_launch(void *slot)
     GroupedDev *gd = (GroupedDev *)d->grouped;
     // the grid does not depend on the table, so a captured launch stays valid
     // when the slot is rewritten; header + capacity descriptors are copied
-    const size_t bytes = sizeof(GHeader) + size_t(s->capacity) * sizeof(GDesc);
+    const size_t bytes = table_bytes(s->capacity);
     return launch_table(gd, *s, s->family, s->variant, gd->grid[s->family][s->variant], bytes,
                         t_tls.stream);
 }

@@ -18,7 +18,8 @@ struct GHeader {
     int count;        // problems in the table
     int total_tiles;  // sum of tiles over problems
     int family;       // dtype family the table was built for
-    int pad[13];
+    int ts_offset;    // byte offset of the int tile_start[count] array
+    int pad[12];
 };
 
 struct GDesc {
@@ -112,23 +113,34 @@ __global__ void __launch_bounds__(256, BODIES::MINB) grouped_kernel(const char *
     const GHeader *h = (const GHeader *)table;
     const GDesc *descs = (const GDesc *)(table + sizeof(GHeader));
     const int total = h->total_tiles, count = h->count;
+    const int *ts = (const int *)(table + h->ts_offset);
+    const int lane = threadIdx.x & 63;
     int t = blockIdx.x;
+    // the next tile id is fetched while the current tile is computed
+    if (threadIdx.x == 0 && t < total) s_next = (int)gridDim.x + atomicAdd(&counters[0], 1);
     while (t < total) {
-        int lo = 0, hi = count - 1;   // last problem whose first tile is <= t
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (descs[mid].tile_start <= t) lo = mid;
-            else hi = mid - 1;
+        // last problem whose first tile is <= t: 64-way search per wave over
+        // the compact prefix array, two dependent loads for up to 4096 problems
+        int lo = 0, hi = count;
+        while (hi - lo > 1) {
+            const int step = (hi - lo + 63) >> 6;
+            const int i = lo + lane * step;
+            const bool le = i < hi && ts[i] <= t;
+            const unsigned long long mask = __ballot(le);
+            const int last = 63 - __builtin_clzll(mask);   // lane 0 always qualifies
+            lo = lo + last * step;
+            hi = min(hi, lo + step);
         }
+        lo = __builtin_amdgcn_readfirstlane(lo);
         const GemmArgs p = descs[lo].a;
         const int body = descs[lo].body;
         int tm, tn;
-        raster(t - descs[lo].tile_start, p.tiles_m, p.tiles_n, p.order, p.group, tm, tn);
+        raster(t - ts[lo], p.tiles_m, p.tiles_n, p.order, p.group, tm, tn);
         BODIES::run(body, p, tm, tn, lds);
-        if (threadIdx.x == 0) s_next = (int)gridDim.x + atomicAdd(&counters[0], 1);
         __syncthreads();
         t = __builtin_amdgcn_readfirstlane(s_next);
         __syncthreads();
+        if (threadIdx.x == 0 && t < total) s_next = (int)gridDim.x + atomicAdd(&counters[0], 1);
     }
     if (threadIdx.x == 0) {
         __threadfence();
