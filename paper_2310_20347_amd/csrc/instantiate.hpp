@@ -7,19 +7,19 @@
 
 namespace mg {
 
-template <class DT, int MC, int NC, int WM, int WN, int ST, bool TA, bool TB, bool VEC>
+template <class DT, int MC, int NC, int WM, int WN, int ST, bool TA, bool TB, bool VEC, int PF>
 static void fill_one(KernelCfg &c)
 {
-    typedef Tile<DT, MC, NC, WM, WN, TA, TB, VEC, ST> T;
+    typedef Tile<DT, MC, NC, WM, WN, TA, TB, VEC, ST, PF> T;
     c.func[2 * TA + TB][VEC] = (const void *)&gemm_tile_kernel<T>;
 }
 
 // Adds configuration (MC, NC, WM, WN, ST) of dtype DT; the element-wise
 // (unaligned) staging variant is compiled only when WITH_SCALAR is set.
-template <class DT, int MC, int NC, int WM, int WN, int ST, bool WITH_SCALAR>
+template <class DT, int MC, int NC, int WM, int WN, int ST, bool WITH_SCALAR, int PF = 1>
 static void add_cfg(std::vector<KernelCfg> &out, int kclass)
 {
-    typedef Tile<DT, MC, NC, WM, WN, false, false, true, ST> T;
+    typedef Tile<DT, MC, NC, WM, WN, false, false, true, ST, PF> T;
     KernelCfg c;
     c.kclass = kclass;
     c.mc = MC;
@@ -31,15 +31,15 @@ static void add_cfg(std::vector<KernelCfg> &out, int kclass)
     c.lds = T::LDS_BYTES;
     c.stages = ST;
     c.kind = 0;
-    fill_one<DT, MC, NC, WM, WN, ST, false, false, true>(c);
-    fill_one<DT, MC, NC, WM, WN, ST, false, true, true>(c);
-    fill_one<DT, MC, NC, WM, WN, ST, true, false, true>(c);
-    fill_one<DT, MC, NC, WM, WN, ST, true, true, true>(c);
+    fill_one<DT, MC, NC, WM, WN, ST, false, false, true, PF>(c);
+    fill_one<DT, MC, NC, WM, WN, ST, false, true, true, PF>(c);
+    fill_one<DT, MC, NC, WM, WN, ST, true, false, true, PF>(c);
+    fill_one<DT, MC, NC, WM, WN, ST, true, true, true, PF>(c);
     if constexpr (WITH_SCALAR) {
-        fill_one<DT, MC, NC, WM, WN, ST, false, false, false>(c);
-        fill_one<DT, MC, NC, WM, WN, ST, false, true, false>(c);
-        fill_one<DT, MC, NC, WM, WN, ST, true, false, false>(c);
-        fill_one<DT, MC, NC, WM, WN, ST, true, true, false>(c);
+        fill_one<DT, MC, NC, WM, WN, ST, false, false, false, PF>(c);
+        fill_one<DT, MC, NC, WM, WN, ST, false, true, false, PF>(c);
+        fill_one<DT, MC, NC, WM, WN, ST, true, false, false, PF>(c);
+        fill_one<DT, MC, NC, WM, WN, ST, true, true, false, PF>(c);
     }
     out.push_back(c);
 }

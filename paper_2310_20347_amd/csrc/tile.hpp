@@ -383,7 +383,11 @@ __device__ __forceinline__ void read_frag(const char *planes, int plane_bytes, i
 // ---------------------------------------------------------------------------
 // The tile: C[m0:m0+MC, n0:n0+NC] = alpha * op(A) op(B) + beta * C.
 // ---------------------------------------------------------------------------
-template <class DT, int MC, int NC, int WM, int WN, bool TA, bool TB, bool VEC, int STAGES>
+// STAGES: LDS buffers (1 or 2).  PF: stages of global loads in flight in
+// registers (1, or 2 with two LDS buffers: the loads of stage s+2 are issued
+// while stage s is multiplied, so they have two stages of MFMA work to land).
+template <class DT, int MC, int NC, int WM, int WN, bool TA, bool TB, bool VEC, int STAGES,
+          int PF = 1>
 struct Tile {
     static constexpr int NT = 64 * WM * WN;
     static constexpr int KC = Kc<DT>::value;
@@ -394,6 +398,8 @@ struct Tile {
     static constexpr int LDS_BYTES = STAGES * STAGE_BYTES;
     static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile must be whole MFMA blocks");
     static_assert(STAGES == 1 || STAGES == 2, "one or two LDS stages");
+    static_assert(PF == 1 || (PF == 2 && STAGES == 2), "two stages in flight need two LDS buffers");
+    static constexpr int MINB = 1;   // workgroups per CU the registers must allow
     static_assert(LDS_BYTES <= 160 * 1024, "LDS budget of one CU");
     typedef typename AccOf<DT>::type Acc;
     typedef Stage<DT, MC, NT, !TA, VEC> StageA;   // A 'N' is contiguous along k
@@ -448,7 +454,46 @@ struct Tile {
             sa.load_any(fullA, A, p.lda, m0, p.m, 0, p.k, tid);
             sb.load_any(fullB, B, p.ldb, n0, p.n, 0, p.k, tid);
         }
-        if constexpr (STAGES == 2) {
+        if constexpr (STAGES == 2 && PF == 2) {
+            // registers: set 0 holds even stages, set 1 odd stages
+            StageA sa1;
+            StageB sb1;
+            if (nk > 1) {
+                sa1.load_any(fullA, A, p.lda, m0, p.m, KC, p.k, tid);
+                sb1.load_any(fullB, B, p.ldb, n0, p.n, KC, p.k, tid);
+            }
+            char *buf0 = lds, *buf1 = lds + STAGE_BYTES;
+            if (nk > 0) {
+                sa.store(buf0, PLANE_A, tid);
+                sb.store(buf0 + DT::PLANES * PLANE_A, PLANE_B, tid);
+            }
+            __syncthreads();
+            for (int s = 0; s < nk; s += 2) {
+                // even stage s is in buf0, stage s+1 in registers set 1
+                if (s + 2 < nk) {
+                    sa.load_any(fullA, A, p.lda, m0, p.m, (s + 2) * KC, p.k, tid);
+                    sb.load_any(fullB, B, p.ldb, n0, p.n, (s + 2) * KC, p.k, tid);
+                }
+                compute(buf0, acc, wm, wn, lane);
+                if (s + 1 < nk) {
+                    sa1.store(buf1, PLANE_A, tid);
+                    sb1.store(buf1 + DT::PLANES * PLANE_A, PLANE_B, tid);
+                }
+                __syncthreads();
+                if (s + 1 >= nk) break;
+                // odd stage s+1 is in buf1, stage s+2 in registers set 0
+                if (s + 3 < nk) {
+                    sa1.load_any(fullA, A, p.lda, m0, p.m, (s + 3) * KC, p.k, tid);
+                    sb1.load_any(fullB, B, p.ldb, n0, p.n, (s + 3) * KC, p.k, tid);
+                }
+                compute(buf1, acc, wm, wn, lane);
+                if (s + 2 < nk) {
+                    sa.store(buf0, PLANE_A, tid);
+                    sb.store(buf0 + DT::PLANES * PLANE_A, PLANE_B, tid);
+                }
+                __syncthreads();
+            }
+        } else if constexpr (STAGES == 2) {
             if (nk > 0) {
                 sa.store(lds, PLANE_A, tid);
                 sb.store(lds + DT::PLANES * PLANE_A, PLANE_B, tid);
@@ -512,7 +557,7 @@ struct Tile {
 
 // One workgroup per tile.
 template <class T>
-__global__ void __launch_bounds__(T::NT) gemm_tile_kernel(GemmArgs p)
+__global__ void __launch_bounds__(T::NT, T::MINB) gemm_tile_kernel(GemmArgs p)
 {
     __shared__ __attribute__((aligned(16))) char lds[T::LDS_BYTES];
     const int nblocks = p.tiles_m * p.tiles_n;
