@@ -56,6 +56,15 @@ def lib():
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built; run paper_2310_20347_amd/build.py "
                            "(or __graft_entry__.build())")
+    # One HIP runtime per process: PyTorch ships its own libamdhip64 under the
+    # same soname, so load PyTorch first and this library binds to the runtime
+    # that PyTorch's device memory and streams belong to.  (Loaded the other
+    # way round, the library's runtime failed to find the device once PyTorch
+    # had initialised it.)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(path)
     L.gemm.argtypes = [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64, _INT]
     L.gemm.restype = _INT

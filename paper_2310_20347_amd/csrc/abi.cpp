@@ -124,6 +124,9 @@ void ensure_registered()
     register_resident_split(g_cfgs);
     register_resident_half(g_cfgs);
     register_resident_byte(g_cfgs);
+    register_direct_f32(g_cfgs);
+    register_direct_half(g_cfgs);
+    register_direct_byte(g_cfgs);
     for (size_t i = 0; i < g_cfgs.size(); ++i) g_by_class[g_cfgs[i].kclass].push_back((int)i);
     g_registered = true;
 }

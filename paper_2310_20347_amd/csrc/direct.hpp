@@ -1,0 +1,335 @@
+// Direct-staged tile: the packing step (section 5.3) done by the memory
+// system.  On gfx950 a global load can write its 16 bytes per lane straight
+// into LDS (lane l -> LDS base + 16*l of a 1 KiB block), so a stage of the
+// A and B panels costs no VGPRs and no LDS store instructions, and a ring of
+// NS stage buffers keeps NS-1 stages of loads in flight while one stage is
+// multiplied: the prefetching of section 6.2 with a depth set by LDS size
+// instead of register count.
+//
+// Used for the input formats that the MFMA consumes as stored (fp32, bf16,
+// fp16, fp8, int8).  The XOR swizzle of the panels is applied on the global side:
+// each lane fetches the vector that belongs at the LDS slot it writes.
+//
+// Panel layouts (one stage, kc = 128 bytes of k per panel row):
+//   k-contiguous operand (A 'N', B 'T'): rows of m (or n), 128 bytes each,
+//     16-byte chunks swizzled as in the register-staged tile; fragments are
+//     read with ds_read_b128.
+//   m/n-contiguous operand (A 'T', B 'N'): kc rows of k, each holding the
+//     panel's m (or n) values; fragments are read with the gfx950 transposing
+//     LDS reads (ds_read_b64_tr_b16 / _b8; lane mapping at read_frag_tr).
+//
+// Edges: a lane whose vector lies wholly outside the operand reads a zero
+// vector instead; a vector that starts inside and ends outside is read whole
+// (it cannot cross a page: it is 16-byte aligned and its first byte is
+// valid).  Its out-of-range part only reaches discarded outputs when it runs
+// past m or n; when it runs past k (a k-contiguous operand with k not a
+// multiple of the vector) the last stage zeroes it in LDS before use.
+#pragma once
+
+#include <limits.h>
+
+#include "tile.hpp"
+
+namespace mg {
+
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) char lds_char;
+typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
+typedef __attribute__((address_space(3))) i32x2 lds_i32x2;
+
+// Sixteen zero bytes: the source of every vector outside the operand.
+static __device__ __attribute__((aligned(16))) u32 g_zero_vec[4];
+
+// One direct global -> LDS load of 16 bytes per lane into the 1 KiB LDS
+// block at `lds_block` (M0 holds its LDS address).  Written as an asm
+// statement rather than the compiler builtin: the compiler does not track
+// which LDS bytes a builtin direct load writes, so it would wait for every
+// load in flight before each transposing LDS read, which defeats the stage
+// ring.  The statement has no register outputs (the data goes to LDS); the
+// ordering against LDS reads is explicit here: wait_vm + s_barrier before a
+// stage is read, and wait_vm<0> before the LDS is reused or released.
+__device__ __forceinline__ void dma16(const void *src, char *lds_block)
+{
+    const u32 m0 = (u32)(uintptr_t)(lds_char *)lds_block;
+    asm volatile("global_load_lds_dwordx4 %0, off" : : "v"(src), "{m0}"(m0) : "memory");
+}
+
+// Wait until at most N of this wave's vector-memory operations (direct loads
+// included) are outstanding.
+template <int N>
+__device__ __forceinline__ void wait_vm()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt is a 6-bit counter");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Chunk swizzle of an m/n-contiguous panel row kr: the rows read together by
+// one 16-lane group of a transposing read land on distinct banks.
+template <int GES>
+__device__ __forceinline__ int mn_swz(int kr)
+{
+    return GES == 4 ? 4 * ((kr >> 2) & 1) : (GES == 2 ? 2 * (kr & 3) : (kr & 7));
+}
+
+template <int GES>
+__device__ __forceinline__ int mn_off(int kr, int row_bytes, int byte)
+{
+    const int lc = byte >> 4;
+    return kr * row_bytes + (((lc & ~7) | ((lc ^ mn_swz<GES>(kr)) & 7)) << 4) + (byte & 15);
+}
+
+// ---------------------------------------------------------------------------
+// One operand panel of a stage: ROWS rows of m (or n) x KC values of k,
+// ROWS/8 blocks of 1 KiB, PER blocks loaded by each of NW waves.
+// ---------------------------------------------------------------------------
+template <class DT, int ROWS, int NW, bool KMODE>
+struct DPanel {
+    static constexpr int GES = DT::GES, KC = 128 / GES, VK = 16 / GES;
+    static constexpr int NB = ROWS / 8;         // 1 KiB blocks per panel
+    static constexpr int PER = NB / NW;         // blocks per wave
+    static constexpr int RB = ROWS * GES;       // m/n mode: bytes per k row
+    static constexpr int CPR = RB / 16;         // m/n mode: chunks per k row
+    static_assert(NB % NW == 0, "panel blocks must divide among the waves");
+    static_assert(KMODE || (RB >= 128 && 64 % CPR == 0), "m/n panel rows of 128..1024 bytes");
+
+    int64_t off[PER];   // lane's byte offset in the operand for the stage at k0 = 0
+    int lim[PER];       // the lane's vector is inside the operand iff k0 < lim
+
+    __device__ __forceinline__ void init(int64_t ld, int row0, int R, int K, int wave, int lane)
+    {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int b = wave * PER + q;
+            if constexpr (KMODE) {
+                const int r = 8 * b + (lane >> 3);
+                const int lc = (lane & 7) ^ swz<4>(r);
+                const int grow = row0 + r, kof = lc * VK;
+                off[q] = ((int64_t)grow * ld + kof) * GES;
+                lim[q] = grow < R ? K - kof : INT_MIN;
+            } else {
+                const int kr = (64 / CPR) * b + lane / CPR, pc = lane % CPR;
+                const int lc = (pc & ~7) | ((pc ^ mn_swz<GES>(kr)) & 7);
+                const int gcol = row0 + lc * VK;
+                off[q] = ((int64_t)kr * ld + gcol) * GES;
+                lim[q] = gcol < R ? K - kr : INT_MIN;
+            }
+        }
+    }
+
+    // Issue this wave's loads of the stage starting at k0 into `panel`.
+    __device__ __forceinline__ void issue(const char *X, int64_t ld, int k0, char *panel,
+                                          int wave) const
+    {
+        const int64_t kstep = KMODE ? (int64_t)k0 * GES : (int64_t)k0 * ld * GES;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const char *src = k0 < lim[q] ? X + off[q] + kstep : (const char *)g_zero_vec;
+            dma16(src, panel + (wave * PER + q) * 1024);
+        }
+    }
+
+    // k-contiguous panel of the last stage, K - k0 values valid with the
+    // chunk at K straddling: zero its values at k >= K.
+    static __device__ __forceinline__ void fix_tail(char *panel, int valid_k, int tid, int nt)
+    {
+        const int lc = valid_k / VK;
+        const int keep = (valid_k % VK) * GES;   // bytes of the chunk to keep, 1..15
+        for (int r = tid; r < ROWS; r += nt) {
+            u32x4 *p = (u32x4 *)(panel + lds_off<4>(r, lc * 16));
+            u32x4 v = *p;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const int nb = keep - 4 * d;
+                const u32 mask = nb >= 4 ? 0xFFFFFFFFu : (nb <= 0 ? 0u : (1u << (8 * nb)) - 1u);
+                v[d] &= mask;
+            }
+            *p = v;
+        }
+    }
+};
+
+// Fragment of the 16-row block at panel offset r0 (m or n) and chunk c of an
+// m/n-contiguous panel, in the same per-lane k assignment as read_frag: lane
+// group g holds k = c*KF + g*KF/4 .. +KF/4-1, in order.  Lane mapping of a
+// transposing read (measured on gfx950): every lane addresses an 8-byte
+// segment of E elements (E = 4 for 16-bit, 8 for 8-bit); within each group of
+// 16 lanes, value j (j < E) returned to lane i is element i mod E of the
+// segment addressed by lane (16/E)*j + i/E.  So lanes (16/E)*j .. +16/E-1
+// address consecutive segments of k row j, and lane i receives column i of
+// E consecutive k rows.  FP32 has no transposing read: one 32-bit read per k
+// row (a 16-lane group reads 64 contiguous bytes of one row; the row swizzle
+// puts the two groups served together on different banks).
+template <class DT, int ROWS>
+__device__ __forceinline__ void read_frag_tr(const char *panel, int r0, int c, int lane,
+                                             u32 (*f)[DT::FDW])
+{
+    constexpr int GES = DT::GES, RB = ROWS * GES;
+    const int g = lane >> 4, s = lane & 15;
+    if constexpr (GES == 4) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const int kr = c * DT::KF + 4 * g + d;
+            f[0][d] = *(const u32 *)(panel + mn_off<4>(kr, RB, (r0 + s) * 4));
+        }
+    } else if constexpr (GES == 2) {
+        // two reads of 4 k values: lane s addresses k row 4h + s/4, elements 4*(s%4)..+3
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int kr = c * DT::KF + 8 * g + 4 * h + (s >> 2);
+            const int byte = (r0 + 4 * (s & 3)) * 2;
+            const i16x4 v =
+                __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)(panel + mn_off<2>(kr, RB, byte)));
+            const u32x2 w = __builtin_bit_cast(u32x2, v);
+            f[0][2 * h] = w[0];
+            f[0][2 * h + 1] = w[1];
+        }
+    } else {
+        // KF/32 reads of 8 k values: lane s addresses k row 8h + s/2, bytes 8*(s%2)..+7
+#pragma unroll
+        for (int h = 0; h < DT::KF / 32; ++h) {
+            const int kr = c * DT::KF + (DT::KF / 4) * g + 8 * h + (s >> 1);
+            const int byte = r0 + 8 * (s & 1);
+            const i32x2 v =
+                __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_i32x2 *)(panel + mn_off<1>(kr, RB, byte)));
+            f[0][2 * h] = (u32)v[0];
+            f[0][2 * h + 1] = (u32)v[1];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The direct-staged tile: C[m0:m0+MC, n0:n0+NC] = alpha op(A) op(B) + beta C
+// with an NS-deep ring of LDS stages.  Requires 16-byte aligned operands and
+// leading dimensions (the vectorised case).
+// ---------------------------------------------------------------------------
+template <class DT, int MC, int NC, int WM, int WN, bool TA, bool TB, int NS>
+struct DTile {
+    static constexpr int NW = WM * WN, NT = 64 * NW;
+    static constexpr int KC = 128 / DT::GES;
+    static constexpr int WTM = MC / WM, WTN = NC / WN;
+    static constexpr int FM = WTM / 16, FN = WTN / 16;
+    static constexpr int PANEL_A = MC * 128, PANEL_B = NC * 128;
+    static constexpr int STAGE_BYTES = PANEL_A + PANEL_B;
+    static constexpr int LDS_BYTES = NS * STAGE_BYTES;
+    static constexpr int MINB = 1;
+    static constexpr int NCH = KC / DT::KF;   // fragment chunks per stage
+    typedef DPanel<DT, MC, NW, !TA> PA;       // A 'N' is contiguous along k
+    typedef DPanel<DT, NC, NW, TB> PB;        // B 'T' is contiguous along k
+    static constexpr int LOADS = PA::PER + PB::PER;
+    static_assert(DT::LES == DT::GES && DT::PLANES == 1, "direct staging keeps the input format");
+    static_assert(NS >= 2 && LDS_BYTES <= 160 * 1024, "LDS budget of one CU");
+    static_assert((NS - 2) * LOADS < 64, "loads in flight must fit the vmcnt counter");
+    static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile must be whole MFMA blocks");
+    typedef typename AccOf<DT>::type Acc;
+
+    static __device__ __forceinline__ void read_chunk(const char *buf, int c, int wm, int wn,
+                                                      int lane, u32 (*fa)[1][DT::FDW],
+                                                      u32 (*fb)[1][DT::FDW])
+    {
+        const char *pa = buf, *pb = buf + PANEL_A;
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+            if constexpr (!TA) read_frag<DT>(pa, PANEL_A, wm * WTM + 16 * i, c, lane, fa[i]);
+            else read_frag_tr<DT, MC>(pa, wm * WTM + 16 * i, c, lane, fa[i]);
+        }
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            if constexpr (TB) read_frag<DT>(pb, PANEL_B, wn * WTN + 16 * j, c, lane, fb[j]);
+            else read_frag_tr<DT, NC>(pb, wn * WTN + 16 * j, c, lane, fb[j]);
+        }
+    }
+
+    // The micro-kernel over one stage; the fragments of chunk c+1 are read
+    // while the MFMAs of chunk c run.
+    static __device__ __forceinline__ void compute(const char *buf, Acc (*acc)[FN], int wm, int wn,
+                                                   int lane)
+    {
+        u32 fa[2][FM][1][DT::FDW], fb[2][FN][1][DT::FDW];
+        read_chunk(buf, 0, wm, wn, lane, fa[0], fb[0]);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            if (c + 1 < NCH) read_chunk(buf, c + 1, wm, wn, lane, fa[(c + 1) & 1], fb[(c + 1) & 1]);
+#pragma unroll
+            for (int st = 0; st < Sub<DT>::value; ++st)
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        mma_step<DT>(acc[i][j], fa[c & 1][i], fb[c & 1][j], st);
+        }
+    }
+
+    static __device__ __forceinline__ void run(const GemmArgs &p, int tm, int tn, char *lds)
+    {
+        const int tid = threadIdx.x, lane = tid & 63;
+        const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int wm = wave % WM, wn = wave / WM;
+        const int m0 = tm * MC, n0 = tn * NC;
+
+        Acc acc[FM][FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+
+        const bool form = p.k > 0 && (DT::INT ? p.ialpha != 0 : p.alpha != 0.0f);
+        const int nk = form ? (p.k + KC - 1) / KC : 0;
+        if (nk > 0) {
+            const char *A = (const char *)p.A;
+            const char *B = (const char *)p.B;
+            PA pa;
+            PB pb;
+            pa.init(p.lda, m0, p.m, p.k, wave, lane);
+            pb.init(p.ldb, n0, p.n, p.k, wave, lane);
+            // stages 0 .. NS-2 in flight; stages past the end load zeros, so
+            // every iteration issues the same number of loads
+#pragma unroll
+            for (int t = 0; t < NS - 1; ++t) {
+                char *buf = lds + t * STAGE_BYTES;
+                pa.issue(A, p.lda, t * KC, buf, wave);
+                pb.issue(B, p.ldb, t * KC, buf + PANEL_A, wave);
+            }
+            const bool ragged = (!TA || TB) && (p.k % PA::VK) != 0;
+            int rd = 0, wr = NS - 1;   // ring buffers: stage being read, stage being loaded
+            for (int s = 0; s < nk; ++s) {
+                wait_vm<(NS - 2) * LOADS>();   // this wave's loads of stage s have landed
+                __builtin_amdgcn_s_barrier();  // ... and every wave's; stage s-1 is consumed
+                pin_order();
+                char *cur = lds + rd * STAGE_BYTES;
+                if (ragged && s == nk - 1) {
+                    const int valid_k = p.k - s * KC;
+                    if constexpr (!TA) PA::fix_tail(cur, valid_k, tid, NT);
+                    if constexpr (TB) PB::fix_tail(cur + PANEL_A, valid_k, tid, NT);
+                    __syncthreads();
+                }
+                char *nxt = lds + wr * STAGE_BYTES;
+                pa.issue(A, p.lda, (s + NS - 1) * KC, nxt, wave);
+                pb.issue(B, p.ldb, (s + NS - 1) * KC, nxt + PANEL_A, wave);
+                pin_order();
+                compute(cur, acc, wm, wn, lane);
+                rd = rd + 1 == NS ? 0 : rd + 1;
+                wr = wr + 1 == NS ? 0 : wr + 1;
+            }
+            // no load may still be writing this workgroup's LDS when it is
+            // reused (next tile of a persistent launch) or released
+            wait_vm<0>();
+            __builtin_amdgcn_s_barrier();
+        }
+        store_c<DT, FM, FN>(p, acc, m0 + wm * WTM, n0 + wn * WTN, lane);
+    }
+};
+
+// One workgroup per tile.
+template <class T>
+__global__ void __launch_bounds__(T::NT, T::MINB) gemm_direct_kernel(GemmArgs p)
+{
+    __shared__ __attribute__((aligned(16))) char lds[T::LDS_BYTES];
+    const int nblocks = p.tiles_m * p.tiles_n;
+    const int t = xcd_remap(blockIdx.x, nblocks);
+    int tm, tn;
+    raster(t, p.tiles_m, p.tiles_n, p.order, p.group, tm, tn);
+    T::run(p, tm, tn, lds);
+}
+
+}  // namespace mg

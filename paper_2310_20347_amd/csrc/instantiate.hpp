@@ -1,25 +1,28 @@
 // Helpers that instantiate the tile kernel for one configuration.
 #pragma once
 
+#include "direct.hpp"
 #include "registry.hpp"
 #include "resident.hpp"
 #include "tile.hpp"
 
 namespace mg {
 
-template <class DT, int MC, int NC, int WM, int WN, int ST, bool TA, bool TB, bool VEC, int PF>
+template <class DT, int MC, int NC, int WM, int WN, int ST, bool TA, bool TB, bool VEC, int PF,
+          bool PEEL>
 static void fill_one(KernelCfg &c)
 {
-    typedef Tile<DT, MC, NC, WM, WN, TA, TB, VEC, ST, PF> T;
+    typedef Tile<DT, MC, NC, WM, WN, TA, TB, VEC, ST, PF, PEEL> T;
     c.func[2 * TA + TB][VEC] = (const void *)&gemm_tile_kernel<T>;
 }
 
 // Adds configuration (MC, NC, WM, WN, ST) of dtype DT; the element-wise
 // (unaligned) staging variant is compiled only when WITH_SCALAR is set.
-template <class DT, int MC, int NC, int WM, int WN, int ST, bool WITH_SCALAR, int PF = 1>
+template <class DT, int MC, int NC, int WM, int WN, int ST, bool WITH_SCALAR, int PF = 1,
+          bool PEEL = true>
 static void add_cfg(std::vector<KernelCfg> &out, int kclass)
 {
-    typedef Tile<DT, MC, NC, WM, WN, false, false, true, ST, PF> T;
+    typedef Tile<DT, MC, NC, WM, WN, false, false, true, ST, PF, PEEL> T;
     KernelCfg c;
     c.kclass = kclass;
     c.mc = MC;
@@ -31,15 +34,15 @@ static void add_cfg(std::vector<KernelCfg> &out, int kclass)
     c.lds = T::LDS_BYTES;
     c.stages = ST;
     c.kind = 0;
-    fill_one<DT, MC, NC, WM, WN, ST, false, false, true, PF>(c);
-    fill_one<DT, MC, NC, WM, WN, ST, false, true, true, PF>(c);
-    fill_one<DT, MC, NC, WM, WN, ST, true, false, true, PF>(c);
-    fill_one<DT, MC, NC, WM, WN, ST, true, true, true, PF>(c);
+    fill_one<DT, MC, NC, WM, WN, ST, false, false, true, PF, PEEL>(c);
+    fill_one<DT, MC, NC, WM, WN, ST, false, true, true, PF, PEEL>(c);
+    fill_one<DT, MC, NC, WM, WN, ST, true, false, true, PF, PEEL>(c);
+    fill_one<DT, MC, NC, WM, WN, ST, true, true, true, PF, PEEL>(c);
     if constexpr (WITH_SCALAR) {
-        fill_one<DT, MC, NC, WM, WN, ST, false, false, false, PF>(c);
-        fill_one<DT, MC, NC, WM, WN, ST, false, true, false, PF>(c);
-        fill_one<DT, MC, NC, WM, WN, ST, true, false, false, PF>(c);
-        fill_one<DT, MC, NC, WM, WN, ST, true, true, false, PF>(c);
+        fill_one<DT, MC, NC, WM, WN, ST, false, false, false, PF, PEEL>(c);
+        fill_one<DT, MC, NC, WM, WN, ST, false, true, false, PF, PEEL>(c);
+        fill_one<DT, MC, NC, WM, WN, ST, true, false, false, PF, PEEL>(c);
+        fill_one<DT, MC, NC, WM, WN, ST, true, true, false, PF, PEEL>(c);
     }
     out.push_back(c);
 }
@@ -84,6 +87,38 @@ static void add_resident_family(std::vector<KernelCfg> &out, int kclass)
     add_resident<DT, 64, 64, 2>(out, kclass);   // A3C2B0
     add_resident<DT, 64, 64, 3>(out, kclass);   // C3A2B0
     add_resident<DT, 64, 64, 4>(out, kclass);   // C3B2A0
+}
+
+// Adds a direct-staged configuration (NS-deep LDS ring, direct.hpp): the
+// vectorised variant of all four transpositions; unaligned operands fall
+// back to the class's configuration 0.
+template <class DT, int MC, int NC, int WM, int WN, int NS, bool TA, bool TB>
+static void fill_direct(KernelCfg &c)
+{
+    typedef DTile<DT, MC, NC, WM, WN, TA, TB, NS> T;
+    c.func[2 * TA + TB][1] = (const void *)&gemm_direct_kernel<T>;
+}
+
+template <class DT, int MC, int NC, int WM, int WN, int NS>
+static void add_direct(std::vector<KernelCfg> &out, int kclass)
+{
+    typedef DTile<DT, MC, NC, WM, WN, false, false, NS> T;
+    KernelCfg c;
+    c.kclass = kclass;
+    c.mc = MC;
+    c.nc = NC;
+    c.kc = T::KC;
+    c.wm = WM;
+    c.wn = WN;
+    c.threads = T::NT;
+    c.lds = T::LDS_BYTES;
+    c.stages = NS;
+    c.kind = 0;
+    fill_direct<DT, MC, NC, WM, WN, NS, false, false>(c);
+    fill_direct<DT, MC, NC, WM, WN, NS, false, true>(c);
+    fill_direct<DT, MC, NC, WM, WN, NS, true, false>(c);
+    fill_direct<DT, MC, NC, WM, WN, NS, true, true>(c);
+    out.push_back(c);
 }
 
 }  // namespace mg

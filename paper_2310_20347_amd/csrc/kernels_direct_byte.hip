@@ -1,0 +1,19 @@
+// FP8 e4m3 / INT8 direct-staged family (global -> LDS loads, NS-deep stage ring).
+#include "instantiate.hpp"
+
+namespace mg {
+template <class DT>
+static void add_byte_direct(std::vector<KernelCfg> &out, int kclass)
+{
+    add_direct<DT, 256, 256, 2, 4, 2>(out, kclass);   // 8 waves of 128x64
+    add_direct<DT, 256, 128, 2, 2, 3>(out, kclass);
+    add_direct<DT, 128, 128, 2, 2, 4>(out, kclass);
+    add_direct<DT, 128, 128, 2, 2, 2>(out, kclass);   // two workgroups per CU
+}
+
+void register_direct_byte(std::vector<KernelCfg> &out)
+{
+    add_byte_direct<TF8>(out, K_F8);
+    add_byte_direct<TI8>(out, K_I8);
+}
+}  // namespace mg

@@ -1,0 +1,20 @@
+// BF16 / FP16 direct-staged family (global -> LDS loads, NS-deep stage ring).
+#include "instantiate.hpp"
+
+namespace mg {
+template <class DT>
+static void add_half_direct(std::vector<KernelCfg> &out, int kclass)
+{
+    add_direct<DT, 256, 256, 2, 4, 2>(out, kclass);   // 8 waves of 128x64
+    add_direct<DT, 256, 256, 2, 2, 2>(out, kclass);   // 4 waves of 128x128
+    add_direct<DT, 256, 128, 2, 2, 3>(out, kclass);
+    add_direct<DT, 128, 128, 2, 2, 4>(out, kclass);
+    add_direct<DT, 128, 128, 2, 2, 2>(out, kclass);   // two workgroups per CU
+}
+
+void register_direct_half(std::vector<KernelCfg> &out)
+{
+    add_half_direct<TBF16>(out, K_BF16);
+    add_half_direct<TF16>(out, K_F16);
+}
+}  // namespace mg

@@ -307,6 +307,17 @@ struct Stage {
 };
 
 // ---------------------------------------------------------------------------
+// Scheduling fence: the compiler may not move instructions across it.  It
+// keeps a stage's global loads ahead of the MFMA chain they are meant to
+// overlap (left alone, the scheduler sinks them next to their LDS stores,
+// which exposes the full memory latency once per stage).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void pin_order()
+{
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// ---------------------------------------------------------------------------
 // One MFMA of the micro-kernel.  A fragment chunk covers KF values of k: a
 // lane of group g = lane/16 holds the k values g*KF/4 .. g*KF/4 + KF/4-1 of
 // its row (A) or column (B); A and B use the same k assignment, so every k of
@@ -381,13 +392,51 @@ __device__ __forceinline__ void read_frag(const char *planes, int plane_bytes, i
 }
 
 // ---------------------------------------------------------------------------
+// Epilogue of a wave's FM x FN accumulator blocks whose top-left corner is
+// (r0, c0): C = alpha * acc + beta * C (C not read when beta == 0; INT8
+// wraps modulo 2^32).  Accumulator layout: lane l, register r -> row
+// 4*(l/16)+r, column l%16 of the block.
+// ---------------------------------------------------------------------------
+template <class DT, int FM, int FN>
+__device__ __forceinline__ void store_c(const GemmArgs &p, const typename AccOf<DT>::type (*acc)[FN],
+                                        int r0, int c0, int lane)
+{
+    const int rbase = r0 + 4 * (lane >> 4);
+    const int cbase = c0 + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rbase + 16 * i + r, col = cbase + 16 * j;
+                if (row < p.m && col < p.n) {
+                    if constexpr (DT::INT) {
+                        int *c = (int *)p.C + (int64_t)row * p.ldc + col;
+                        u32 v = (u32)p.ialpha * (u32)acc[i][j][r];
+                        if (p.ibeta != 0) v += (u32)p.ibeta * (u32)(*c);
+                        *c = (int)v;
+                    } else {
+                        float *c = (float *)p.C + (int64_t)row * p.ldc + col;
+                        float v = p.alpha * acc[i][j][r];
+                        if (p.beta != 0.0f) v = __builtin_fmaf(p.beta, *c, v);
+                        *c = v;
+                    }
+                }
+            }
+}
+
+// ---------------------------------------------------------------------------
 // The tile: C[m0:m0+MC, n0:n0+NC] = alpha * op(A) op(B) + beta * C.
 // ---------------------------------------------------------------------------
 // STAGES: LDS buffers (1 or 2).  PF: stages of global loads in flight in
 // registers (1, or 2 with two LDS buffers: the loads of stage s+2 are issued
 // while stage s is multiplied, so they have two stages of MFMA work to land).
+// PEEL: interior tiles run their full stages in a separate loop with
+// unchecked loads held ahead of the MFMA chain by scheduling fences (more
+// registers live across the chain; off where that costs occupancy).
 template <class DT, int MC, int NC, int WM, int WN, bool TA, bool TB, bool VEC, int STAGES,
-          int PF = 1>
+          int PF = 1, bool PEEL = true>
 struct Tile {
     static constexpr int NT = 64 * WM * WN;
     static constexpr int KC = Kc<DT>::value;
@@ -450,10 +499,17 @@ struct Tile {
         StageA sa;
         StageB sb;
         const bool fullA = m0 + MC <= p.m, fullB = n0 + NC <= p.n;   // panel rows in bounds
+        // Stages [0, kfull) of an interior tile take the unchecked vector
+        // loads; the main loops below run only those, with no branch between
+        // load variants, so each loaded register flows straight to its LDS
+        // store and the loads stay in flight across the MFMA chain.  The
+        // remaining (partial or edge) stages run the checked loop.
+        const int kfull = (PEEL && VEC && fullA && fullB) ? p.k / KC : 0;
         if (nk > 0) {
             sa.load_any(fullA, A, p.lda, m0, p.m, 0, p.k, tid);
             sb.load_any(fullB, B, p.ldb, n0, p.n, 0, p.k, tid);
         }
+        int s = 0;
         if constexpr (STAGES == 2 && PF == 2) {
             // registers: set 0 holds even stages, set 1 odd stages
             StageA sa1;
@@ -468,8 +524,22 @@ struct Tile {
                 sb.store(buf0 + DT::PLANES * PLANE_A, PLANE_B, tid);
             }
             __syncthreads();
-            for (int s = 0; s < nk; s += 2) {
-                // even stage s is in buf0, stage s+1 in registers set 1
+            // even stage s is in buf0, stage s+1 in register set 1
+            for (; s + 3 < kfull; s += 2) {
+                sa.load_fast(A, p.lda, m0, (s + 2) * KC, tid);
+                sb.load_fast(B, p.ldb, n0, (s + 2) * KC, tid);
+                compute(buf0, acc, wm, wn, lane);
+                sa1.store(buf1, PLANE_A, tid);
+                sb1.store(buf1 + DT::PLANES * PLANE_A, PLANE_B, tid);
+                __syncthreads();
+                sa1.load_fast(A, p.lda, m0, (s + 3) * KC, tid);
+                sb1.load_fast(B, p.ldb, n0, (s + 3) * KC, tid);
+                compute(buf1, acc, wm, wn, lane);
+                sa.store(buf0, PLANE_A, tid);
+                sb.store(buf0 + DT::PLANES * PLANE_A, PLANE_B, tid);
+                __syncthreads();
+            }
+            for (; s < nk; s += 2) {
                 if (s + 2 < nk) {
                     sa.load_any(fullA, A, p.lda, m0, p.m, (s + 2) * KC, p.k, tid);
                     sb.load_any(fullB, B, p.ldb, n0, p.n, (s + 2) * KC, p.k, tid);
@@ -481,7 +551,7 @@ struct Tile {
                 }
                 __syncthreads();
                 if (s + 1 >= nk) break;
-                // odd stage s+1 is in buf1, stage s+2 in registers set 0
+                // odd stage s+1 is in buf1, stage s+2 in register set 0
                 if (s + 3 < nk) {
                     sa1.load_any(fullA, A, p.lda, m0, p.m, (s + 3) * KC, p.k, tid);
                     sb1.load_any(fullB, B, p.ldb, n0, p.n, (s + 3) * KC, p.k, tid);
@@ -499,7 +569,19 @@ struct Tile {
                 sb.store(lds + DT::PLANES * PLANE_A, PLANE_B, tid);
             }
             __syncthreads();
-            for (int s = 0; s < nk; ++s) {
+            for (; s + 1 < kfull; ++s) {
+                char *cur = lds + (s & 1) * STAGE_BYTES;
+                char *nxt = lds + ((s + 1) & 1) * STAGE_BYTES;
+                sa.load_fast(A, p.lda, m0, (s + 1) * KC, tid);
+                sb.load_fast(B, p.ldb, n0, (s + 1) * KC, tid);
+                pin_order();
+                compute(cur, acc, wm, wn, lane);
+                pin_order();
+                sa.store(nxt, PLANE_A, tid);
+                sb.store(nxt + DT::PLANES * PLANE_A, PLANE_B, tid);
+                __syncthreads();
+            }
+            for (; s < nk; ++s) {
                 char *cur = lds + (s & 1) * STAGE_BYTES;
                 char *nxt = lds + ((s + 1) & 1) * STAGE_BYTES;
                 if (s + 1 < nk) {
@@ -514,7 +596,16 @@ struct Tile {
                 __syncthreads();
             }
         } else {
-            for (int s = 0; s < nk; ++s) {
+            for (; s + 1 < kfull; ++s) {
+                sa.store(lds, PLANE_A, tid);
+                sb.store(lds + DT::PLANES * PLANE_A, PLANE_B, tid);
+                __syncthreads();
+                sa.load_fast(A, p.lda, m0, (s + 1) * KC, tid);
+                sb.load_fast(B, p.ldb, n0, (s + 1) * KC, tid);
+                compute(lds, acc, wm, wn, lane);
+                __syncthreads();
+            }
+            for (; s < nk; ++s) {
                 sa.store(lds, PLANE_A, tid);
                 sb.store(lds + DT::PLANES * PLANE_A, PLANE_B, tid);
                 __syncthreads();
@@ -527,31 +618,7 @@ struct Tile {
             }
         }
 
-        // Epilogue: C = alpha * acc + beta * C (C not read when beta == 0).
-        // Accumulator block layout: lane l, register r -> row 4*(l/16)+r, col l%16.
-        const int rbase = m0 + wm * WTM + 4 * (lane >> 4);
-        const int cbase = n0 + wn * WTN + (lane & 15);
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int j = 0; j < FN; ++j)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = rbase + 16 * i + r, col = cbase + 16 * j;
-                    if (row < p.m && col < p.n) {
-                        if constexpr (DT::INT) {
-                            int *c = (int *)p.C + (int64_t)row * p.ldc + col;
-                            u32 v = (u32)p.ialpha * (u32)acc[i][j][r];
-                            if (p.ibeta != 0) v += (u32)p.ibeta * (u32)(*c);
-                            *c = (int)v;
-                        } else {
-                            float *c = (float *)p.C + (int64_t)row * p.ldc + col;
-                            float v = p.alpha * acc[i][j][r];
-                            if (p.beta != 0.0f) v = __builtin_fmaf(p.beta, *c, v);
-                            *c = v;
-                        }
-                    }
-                }
+        store_c<DT, FM, FN>(p, acc, m0 + wm * WTM, n0 + wn * WTN, lane);
     }
 };
 

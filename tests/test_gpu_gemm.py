@@ -69,6 +69,53 @@ def test_every_configuration_and_raster_order(dtype):
         assert np.array_equal(r, results[0])
 
 
+@pytest.mark.parametrize("dtype", [mg.GEMM_F32, mg.GEMM_BF16, mg.GEMM_F16, mg.GEMM_F8E4M3,
+                                   mg.GEMM_I8], ids=lambda d: mg.DTYPE_NAMES[d])
+def test_every_configuration_every_layout_ragged(dtype):
+    """Every configuration (register-staged, operand-resident and the LDS-ring
+    ones fed by direct global->LDS loads) in all four layouts, with m, n and k
+    ragged against the tile, the 16-byte vector and the k stage, and leading
+    dimensions that are 16-byte multiples (so every configuration runs its
+    own vectorised staging): exact on small integers."""
+    import torch
+    from gemm_cases import decode, encode, make_operands, stored
+    pad = 7   # dimensions = 9 mod 16, leading dimensions = 0 mod 16
+    for (m, n, k) in [(297, 265, 1001), (41, 57, 41)]:
+        for ta, tb in TRANS:
+            c = Case(dtype, ta, tb, m, n, k, 1.0, -1.0, pad=pad, dist="ints", seed=11)
+            a32, b32, c0 = make_operands(c)
+            lda = (m if ta == "T" else k) + pad
+            ldb = (k if tb == "T" else n) + pad
+            ldc = n + pad
+            As, Bs = stored(encode(a32, dtype), ta, lda), stored(encode(b32, dtype), tb, ldb)
+            # padding between rows holds NaN (int8: 127): a vector that runs
+            # past m, n or k must not leak it into a valid output
+            junk = {mg.GEMM_F32: np.nan, mg.GEMM_BF16: 0x7FC0, mg.GEMM_F16: 0x7E00,
+                    mg.GEMM_F8E4M3: 0x7F, mg.GEMM_I8: 127}[dtype]
+            As[:, (m if ta == "T" else k):] = junk
+            Bs[:, (k if tb == "T" else n):] = junk
+            Cs0 = stored(c0, "N", ldc)
+            if dtype == mg.GEMM_I8:
+                ref = oracle.gemm_i8(ta, tb, m, n, k, 1, As, lda, Bs, ldb, -1, Cs0, ldc)
+            else:
+                ref = oracle.gemm_f64(ta, tb, m, n, k, 1.0, decode(As, dtype), lda,
+                                      decode(Bs, dtype), ldb, -1.0, Cs0, ldc)
+            dA, dB = to_device(As), to_device(Bs)
+            try:
+                for cfg in range(mg.num_configs(dtype)):
+                    mg.force_config(dtype, cfg, cfg % 2)
+                    dC = to_device(Cs0.copy())
+                    print(f"cfg {cfg} {ta}{tb} {m}x{n}x{k}", flush=True)
+                    mg.gemm(ta, tb, m, n, k, 1.0, dA, lda, dB, ldb, -1.0, dC, ldc, dtype)
+                    torch.cuda.synchronize()
+                    assert mg.last_config()["cfg"] == cfg
+                    C = dC.cpu().numpy().reshape(m, ldc)[:, :n]
+                    assert np.array_equal(C, np.asarray(ref).astype(C.dtype)), \
+                        f"cfg {cfg} {ta}{tb} {m}x{n}x{k} not exact"
+            finally:
+                mg.force_config(dtype, -1, 0)
+
+
 @pytest.mark.parametrize("dtype", ALL_DTYPES, ids=lambda d: mg.DTYPE_NAMES[d])
 @pytest.mark.parametrize("ta,tb", TRANS)
 def test_identity_and_permutation_pins(dtype, ta, tb):
