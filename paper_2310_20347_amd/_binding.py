@@ -181,12 +181,23 @@ def _problems(problems: Sequence[Problem]):
     return arr
 
 
-def gemm_grouped(problems: Sequence[Problem], dtype: int, stream: Any = None,
-                 check: bool = True) -> int:
-    """All problems in one persistent launch on the current (or given) stream."""
+class PackedProblems:
+    """A problem list marshalled once into the C array gemm_grouped reads, for
+    callers that launch the same list repeatedly."""
+
+    def __init__(self, problems: Sequence[Problem]):
+        self.count = len(problems)
+        self.array = _problems(problems)
+        self._keep = list(problems)
+
+
+def gemm_grouped(problems, dtype: int, stream: Any = None, check: bool = True) -> int:
+    """All problems (a sequence of Problem, or PackedProblems) in one
+    persistent launch on the current (or given) stream."""
     set_stream(stream)
-    arr = _problems(problems)
-    rc = lib().gemm_grouped(len(problems), arr, int(dtype))
+    if not isinstance(problems, PackedProblems):
+        problems = PackedProblems(problems)
+    rc = lib().gemm_grouped(problems.count, problems.array, int(dtype))
     return _check(rc, "gemm_grouped") if check else rc
 
 

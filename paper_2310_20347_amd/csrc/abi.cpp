@@ -127,6 +127,22 @@ void ensure_registered()
     register_direct_f32(g_cfgs);
     register_direct_half(g_cfgs);
     register_direct_byte(g_cfgs);
+    // packed split: every direct bf16 tile, run on operands that a packing
+    // pass has split into bf16 pieces (three- and six-term classes)
+    const size_t nbase = g_cfgs.size();
+    for (int cls : {K_SPLIT2, K_SPLIT3}) {
+        for (size_t i = 0; i < nbase; ++i) {
+            if (g_cfgs[i].kclass != K_BF16 || !g_cfgs[i].direct) continue;
+            KernelCfg p = g_cfgs[i];
+            p.kclass = cls;
+            p.kind = 5;
+            p.direct = false;
+            p.packed = (int)i;
+            for (int t = 0; t < 4; ++t)
+                for (int v = 0; v < 2; ++v) p.func[t][v] = split_pack_entry();
+            g_cfgs.push_back(p);
+        }
+    }
     for (size_t i = 0; i < g_cfgs.size(); ++i) g_by_class[g_cfgs[i].kclass].push_back((int)i);
     g_registered = true;
 }
@@ -351,8 +367,73 @@ void select_config(int kclass, int trans, int64_t m, int64_t n, int64_t k, int c
     heuristic(kclass, m, n, cus, id, order, group);
 }
 
+// Grow-only workspace of stream s on device d (NULL when it cannot be had).
+void *stream_workspace(DevState *d, hipStream_t s, size_t bytes)
+{
+    std::lock_guard<std::mutex> g(d->ws_mu);
+    std::pair<void *, size_t> &w = d->ws[s];
+    if (w.second >= bytes) return w.first;
+    if (w.first) {
+        // earlier GEMMs on this stream may still read the old buffer
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(w.first);
+        w = {nullptr, 0};
+    }
+    const size_t gran = size_t(64) << 20;
+    const size_t want = (bytes + gran - 1) / gran * gran;
+    void *p = nullptr;
+    const hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        t_tls.hip_err = (int)e;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    w = {p, want};
+    return p;
+}
+
+void free_workspaces(DevState *d)
+{
+    std::lock_guard<std::mutex> g(d->ws_mu);
+    for (auto &kv : d->ws)
+        if (kv.second.first) (void)hipFree(kv.second.first);
+    d->ws.clear();
+}
+
+// Packed split product: pack op(A) and op(B) into k-contiguous bf16 pieces
+// in the stream's workspace, then run the bf16 tile c.packed ('N','T') over
+// the packed k.
+static int launch_packed(const KernelCfg &c, int trans, const GemmArgs &a, hipStream_t s)
+{
+    const int terms = a.terms;
+    const int64_t kp = packed_k(a.k, terms);
+    if (kp > 0x7FFFFFFF || terms <= 0) return kPackUnavailable;
+    const size_t abytes = (size_t(a.m) * kp * 2 + 255) / 256 * 256;
+    const size_t bbytes = size_t(a.n) * kp * 2;
+    DevState *d = nullptr;
+    int rc = device_state(&d);
+    if (rc != GEMM_OK) return rc;
+    char *ws = (char *)stream_workspace(d, s, abytes + bbytes);
+    if (!ws) return kPackUnavailable;
+    unsigned short *pa = (unsigned short *)ws, *pb = (unsigned short *)(ws + abytes);
+    const bool ta = (trans >> 1) != 0, tb = (trans & 1) != 0;
+    rc = launch_split_pack((const float *)a.A, a.lda, !ta, a.m, a.k, terms, true, pa, s);
+    if (rc == GEMM_E_UNSUPPORTED) return kPackUnavailable;
+    if (rc != GEMM_OK) return rc;
+    rc = launch_split_pack((const float *)a.B, a.ldb, tb, a.n, a.k, terms, false, pb, s);
+    if (rc != GEMM_OK) return rc;
+    GemmArgs b = a;
+    b.A = pa;
+    b.lda = kp;
+    b.B = pb;
+    b.ldb = kp;
+    b.k = (int)kp;
+    return launch_gemm(g_cfgs[c.packed], 1, true, b, s);
+}
+
 int launch_gemm(const KernelCfg &c, int trans, bool vec, const GemmArgs &a, hipStream_t s)
 {
+    if (c.packed >= 0) return launch_packed(c, trans, a, s);
     const void *f = c.func[trans][vec ? 1 : 0];
     if (!f) return GEMM_E_UNSUPPORTED;
     const int64_t blocks = int64_t(a.tiles_m) * a.tiles_n;
@@ -452,6 +533,15 @@ int gemm(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha
                               d->cus, a, trans, vec, cfg, kclass);
     if (reg < 0) return GEMM_E_UNSUPPORTED;
     rc = launch_gemm(g_cfgs[reg], trans, vec, a, s);
+    if (rc == kPackUnavailable) {
+        // no workspace for the packed split: the fused split tile instead
+        const int saved = t_tls.force_id[kclass];
+        t_tls.force_id[kclass] = vec ? 1 : 0;
+        const int reg2 = plan_gemm(dtype, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta,
+                                   C, ldc, d->cus, a, trans, vec, cfg, kclass);
+        t_tls.force_id[kclass] = saved;
+        rc = reg2 < 0 ? GEMM_E_UNSUPPORTED : launch_gemm(g_cfgs[reg2], trans, vec, a, s);
+    }
     if (rc == GEMM_OK) {
         t_tls.last[0] = dtype;
         t_tls.last[1] = cfg;
@@ -483,7 +573,10 @@ int gemm_init(const char *tune_table_path)
 
 void gemm_shutdown(void)
 {
-    for (int i = 0; i < kMaxDevices; ++i) grouped_device_free(&g_dev[i]);
+    for (int i = 0; i < kMaxDevices; ++i) {
+        grouped_device_free(&g_dev[i]);
+        free_workspaces(&g_dev[i]);
+    }
 }
 
 const char *gemm_strerror(int code)

@@ -6,6 +6,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "registry.hpp"
@@ -22,7 +23,15 @@ struct DevState {
     // grouped launches: device descriptor tables and pinned host staging
     bool grouped_ready = false;
     void *grouped = nullptr;
+    // packed split operands: one grow-only workspace per stream (work on one
+    // stream is ordered, so its GEMMs can share it)
+    std::mutex ws_mu;
+    std::map<hipStream_t, std::pair<void *, size_t>> ws;
 };
+
+// Internal status of launch_gemm: a packed configuration could not get its
+// workspace (the caller falls back to a fused configuration).
+constexpr int kPackUnavailable = 100;
 
 // Tuning table key: kernel class, trans index (2*tA + tB), log2 size buckets.
 struct TuneKey {
@@ -78,5 +87,13 @@ int launch_gemm(const KernelCfg &c, int trans, bool vec, const GemmArgs &a, hipS
 // grouped.hip
 int grouped_device_init(DevState *d);
 void grouped_device_free(DevState *d);
+
+// pack.hip: split-product packing
+int64_t packed_k(int64_t k, int terms);
+int launch_split_pack(const float *X, int64_t ld, bool kmode, int64_t rows, int64_t k, int terms,
+                      bool a_side, unsigned short *out, hipStream_t s);
+const void *split_pack_entry();
+void *stream_workspace(DevState *d, hipStream_t s, size_t bytes);
+void free_workspaces(DevState *d);
 
 }  // namespace mg

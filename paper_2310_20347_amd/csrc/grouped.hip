@@ -38,6 +38,7 @@ GroupedFamily grouped_family(int fam)
 
 constexpr int64_t kCapacity = 8192;   // problems per descriptor table
 constexpr int kRotating = 4;          // rotating slots of gemm_grouped per device
+constexpr int kCounterInts = 16;      // kGroups tile counters + finished count, padded
 // header, descriptors, then the compact tile_start array (one int per problem)
 constexpr size_t table_bytes(int64_t cap) { return sizeof(GHeader) + size_t(cap) * (sizeof(GDesc) + 4); }
 constexpr size_t kTableBytes = table_bytes(kCapacity);
@@ -45,7 +46,7 @@ constexpr size_t kTableBytes = table_bytes(kCapacity);
 struct Slot {
     char *host = nullptr;     // pinned staging
     char *dev = nullptr;      // device table
-    int *counters = nullptr;  // device {next tile, finished workgroups}
+    int *counters = nullptr;  // device {next position per XCD group [8], finished workgroups}
     hipEvent_t done = nullptr;
     bool used = false;
     int family = -1;
@@ -81,8 +82,8 @@ static int slot_alloc(Slot &s, int device)
     s.device = device;
     if ((e = hipHostMalloc((void **)&s.host, kTableBytes, hipHostMallocDefault)) != hipSuccess) goto fail;
     if ((e = hipMalloc((void **)&s.dev, kTableBytes)) != hipSuccess) goto fail;
-    if ((e = hipMalloc((void **)&s.counters, 2 * sizeof(int))) != hipSuccess) goto fail;
-    if ((e = hipMemset(s.counters, 0, 2 * sizeof(int))) != hipSuccess) goto fail;
+    if ((e = hipMalloc((void **)&s.counters, kCounterInts * sizeof(int))) != hipSuccess) goto fail;
+    if ((e = hipMemset(s.counters, 0, kCounterInts * sizeof(int))) != hipSuccess) goto fail;
     if ((e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess) goto fail;
     if ((e = hipDeviceSynchronize()) != hipSuccess) goto fail;
     return GEMM_OK;

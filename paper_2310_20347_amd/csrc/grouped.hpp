@@ -2,14 +2,15 @@
 // launch.  The host writes a descriptor table (one GemmArgs per problem plus
 // the compiled tile body to use and the problem's first global tile id).
 // Each workgroup repeatedly takes a global tile id, finds its problem by
-// binary search over the tile prefix, maps the local id through that
-// problem's raster order and runs the tile body (the same C-resident tile as
-// the single-GEMM kernel).  Tile ids beyond the first gridDim.x come from an
-// atomic counter; the last workgroup to finish resets the counters to zero,
-// so a launch leaves them ready for the next one (no memset node is needed,
-// which keeps the launch capturable in a graph).
+// search over the tile prefix, maps the local id through that problem's
+// raster order and runs the tile body (the same C-resident tile as the
+// single-GEMM kernel).  Tile ids beyond each workgroup's first come from
+// atomic counters (one per XCD group); the last workgroup to finish resets
+// the counters to zero, so a launch leaves them ready for the next one (no
+// memset node is needed, which keeps the launch capturable in a graph).
 #pragma once
 
+#include "direct.hpp"
 #include "tile.hpp"
 
 namespace mg {
@@ -31,12 +32,30 @@ struct GDesc {
 static_assert(sizeof(GHeader) == 64, "header is 64 bytes");
 static_assert(sizeof(GDesc) % 16 == 0, "descriptors are 16-byte aligned");
 
-// A tile shape of a family: element type, mc x nc, LDS stages.
+// A tile shape of a family: element type, mc x nc, LDS stages (register-
+// staged tile; `run` is its 'N','N' vectorised body).
 template <class DT, int MC, int NC, int ST>
 struct Shape {
     typedef DT dt;
     static constexpr int mc = MC, nc = NC, st = ST;
-    static constexpr int lds = Tile<DT, MC, NC, 2, 2, false, false, true, ST>::LDS_BYTES;
+    typedef Tile<DT, MC, NC, 2, 2, false, false, true, ST> NN;
+    static constexpr int lds = NN::LDS_BYTES;
+    static __device__ __forceinline__ void run(const GemmArgs &p, int tm, int tn, char *l)
+    {
+        NN::run(p, tm, tn, l);
+    }
+};
+// A direct-staged 'N','N' tile shape (NS-deep LDS ring, 16-byte aligned operands).
+template <class DT, int MC, int NC, int NS>
+struct DShape {
+    typedef DT dt;
+    static constexpr int mc = MC, nc = NC;
+    typedef DTile<DT, MC, NC, 2, 2, false, false, NS> NN;
+    static constexpr int lds = NN::LDS_BYTES;
+    static __device__ __forceinline__ void run(const GemmArgs &p, int tm, int tn, char *l)
+    {
+        NN::run(p, tm, tn, l);
+    }
 };
 struct NoShape {
     static constexpr int lds = 0;
@@ -97,13 +116,24 @@ struct LeanBodies {
     {
         if constexpr (SB::lds > 0) {
             if (body == 1) {
-                Tile<typename SB::dt, SB::mc, SB::nc, 2, 2, false, false, true, SB::st>::run(p, tm, tn, lds);
+                SB::run(p, tm, tn, lds);
                 return;
             }
         }
-        Tile<typename SA::dt, SA::mc, SA::nc, 2, 2, false, false, true, SA::st>::run(p, tm, tn, lds);
+        SA::run(p, tm, tn, lds);
     }
 };
+
+// Tile ids are dealt to the XCDs in chunks of kChunk consecutive ids (about
+// the number of workgroups one XCD runs at a time), so the tiles an XCD works
+// on together are neighbours in their problem's raster and share A and B
+// panels in that XCD's L2.  Workgroups are dispatched round-robin over the
+// XCDs (block b -> XCD b % 8), so group g = b % L collects the workgroups of
+// one XCD; with fewer than 8 workgroups, L = grid size and every group still
+// has a workgroup.  counters[g] hands out group g's chunk positions;
+// counters[8] counts finished workgroups.
+constexpr int kChunk = 64;
+constexpr int kGroups = 8;
 
 template <class BODIES>
 __global__ void __launch_bounds__(256, BODIES::MINB) grouped_kernel(const char *table, int *counters)
@@ -115,9 +145,14 @@ __global__ void __launch_bounds__(256, BODIES::MINB) grouped_kernel(const char *
     const int total = h->total_tiles, count = h->count;
     const int *ts = (const int *)(table + h->ts_offset);
     const int lane = threadIdx.x & 63;
-    int t = blockIdx.x;
+    const int L = min((int)gridDim.x, kGroups);
+    const int g = blockIdx.x % L;
+    const int members = ((int)gridDim.x - g + L - 1) / L;   // workgroups of group g
+    // position v of group g -> global tile id
+    auto tile_of = [&](int v) { return ((v / kChunk) * L + g) * kChunk + v % kChunk; };
+    int t = tile_of((int)blockIdx.x / L);
     // the next tile id is fetched while the current tile is computed
-    if (threadIdx.x == 0 && t < total) s_next = (int)gridDim.x + atomicAdd(&counters[0], 1);
+    if (threadIdx.x == 0 && t < total) s_next = tile_of(members + atomicAdd(&counters[g], 1));
     while (t < total) {
         // last problem whose first tile is <= t: 64-way search per wave over
         // the compact prefix array, two dependent loads for up to 4096 problems
@@ -140,13 +175,13 @@ __global__ void __launch_bounds__(256, BODIES::MINB) grouped_kernel(const char *
         __syncthreads();
         t = __builtin_amdgcn_readfirstlane(s_next);
         __syncthreads();
-        if (threadIdx.x == 0 && t < total) s_next = (int)gridDim.x + atomicAdd(&counters[0], 1);
+        if (threadIdx.x == 0 && t < total) s_next = tile_of(members + atomicAdd(&counters[g], 1));
     }
     if (threadIdx.x == 0) {
         __threadfence();
-        if (atomicAdd(&counters[1], 1) == (int)gridDim.x - 1) {
-            atomicExch(&counters[0], 0);
-            atomicExch(&counters[1], 0);
+        if (atomicAdd(&counters[kGroups], 1) == (int)gridDim.x - 1) {
+            for (int i = 0; i < kGroups; ++i) atomicExch(&counters[i], 0);
+            atomicExch(&counters[kGroups], 0);
         }
     }
 }

@@ -114,6 +114,7 @@ static void add_direct(std::vector<KernelCfg> &out, int kclass)
     c.lds = T::LDS_BYTES;
     c.stages = NS;
     c.kind = 0;
+    c.direct = true;
     fill_direct<DT, MC, NC, WM, WN, NS, false, false>(c);
     fill_direct<DT, MC, NC, WM, WN, NS, false, true>(c);
     fill_direct<DT, MC, NC, WM, WN, NS, true, false>(c);

@@ -27,7 +27,9 @@ struct KernelCfg {
     int threads = 0;
     int lds = 0;            // bytes of LDS per workgroup
     int stages = 0;
-    int kind = 0;           // 0: C resident (registers); 1: A resident; 2: B resident
+    int kind = 0;           // 0: C resident (registers); 1..4: operand resident; 5: packed split
+    bool direct = false;    // stages fed by direct global -> LDS loads
+    int packed = -1;        // packed split: registry index of the bf16 tile run on the packed operands
     // kernel entry per [trans index = 2*transA + transB][vectorised staging]
     const void *func[4][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr},
                               {nullptr, nullptr}};

@@ -69,8 +69,9 @@ def test_every_configuration_and_raster_order(dtype):
         assert np.array_equal(r, results[0])
 
 
-@pytest.mark.parametrize("dtype", [mg.GEMM_F32, mg.GEMM_BF16, mg.GEMM_F16, mg.GEMM_F8E4M3,
-                                   mg.GEMM_I8], ids=lambda d: mg.DTYPE_NAMES[d])
+@pytest.mark.parametrize("dtype", [mg.GEMM_F32, mg.GEMM_F32_BF16X3, mg.GEMM_F32_BF16X6,
+                                   mg.GEMM_BF16, mg.GEMM_F16, mg.GEMM_F8E4M3, mg.GEMM_I8],
+                         ids=lambda d: mg.DTYPE_NAMES[d])
 def test_every_configuration_every_layout_ragged(dtype):
     """Every configuration (register-staged, operand-resident and the LDS-ring
     ones fed by direct global->LDS loads) in all four layouts, with m, n and k
@@ -90,8 +91,8 @@ def test_every_configuration_every_layout_ragged(dtype):
             As, Bs = stored(encode(a32, dtype), ta, lda), stored(encode(b32, dtype), tb, ldb)
             # padding between rows holds NaN (int8: 127): a vector that runs
             # past m, n or k must not leak it into a valid output
-            junk = {mg.GEMM_F32: np.nan, mg.GEMM_BF16: 0x7FC0, mg.GEMM_F16: 0x7E00,
-                    mg.GEMM_F8E4M3: 0x7F, mg.GEMM_I8: 127}[dtype]
+            junk = {mg.GEMM_BF16: 0x7FC0, mg.GEMM_F16: 0x7E00, mg.GEMM_F8E4M3: 0x7F,
+                    mg.GEMM_I8: 127}.get(dtype, np.nan)
             As[:, (m if ta == "T" else k):] = junk
             Bs[:, (k if tb == "T" else n):] = junk
             Cs0 = stored(c0, "N", ldc)
@@ -101,8 +102,10 @@ def test_every_configuration_every_layout_ragged(dtype):
                 ref = oracle.gemm_f64(ta, tb, m, n, k, 1.0, decode(As, dtype), lda,
                                       decode(Bs, dtype), ldb, -1.0, Cs0, ldc)
             dA, dB = to_device(As), to_device(Bs)
+            # the split dtype takes the six-term family (and its configurations) when k < 64
+            fam = mg.GEMM_F32_BF16X6 if (dtype == mg.GEMM_F32_BF16X3 and k < 64) else dtype
             try:
-                for cfg in range(mg.num_configs(dtype)):
+                for cfg in range(mg.num_configs(fam)):
                     mg.force_config(dtype, cfg, cfg % 2)
                     dC = to_device(Cs0.copy())
                     print(f"cfg {cfg} {ta}{tb} {m}x{n}x{k}", flush=True)
@@ -114,6 +117,39 @@ def test_every_configuration_every_layout_ragged(dtype):
                         f"cfg {cfg} {ta}{tb} {m}x{n}x{k} not exact"
             finally:
                 mg.force_config(dtype, -1, 0)
+
+
+@pytest.mark.parametrize("dtype", [mg.GEMM_F32_BF16X3, mg.GEMM_F32_BF16X6],
+                         ids=lambda d: mg.DTYPE_NAMES[d])
+@pytest.mark.parametrize("ta,tb", TRANS)
+def test_packed_split_equals_fused_split_bitwise(dtype, ta, tb):
+    """The packed split (a packing pass writes the bf16 pieces, then a bf16
+    tile multiplies them) issues the same MFMA sequence on every accumulator
+    as the fused split tile: equal bits, on normal inputs with ragged k."""
+    import torch
+    from gemm_cases import encode, make_operands, stored
+    m, n, k = 200, 300, 515
+    c = Case(dtype, ta, tb, m, n, k, 1.25, -0.5, dist="normal", seed=12)
+    a32, b32, c0 = make_operands(c)
+    lda, ldb, ldc = (m if ta == "T" else k), (k if tb == "T" else n), n
+    dA = to_device(stored(encode(a32, dtype), ta, lda))
+    dB = to_device(stored(encode(b32, dtype), tb, ldb))
+    packed = [i for i in range(mg.num_configs(dtype)) if mg.config_info(dtype, i)["kind"] == 5]
+    assert packed, "no packed split configuration registered"
+    outs = {}
+    try:
+        for cfg in [0] + packed:   # configuration 0 also takes unaligned operands
+            mg.force_config(dtype, cfg, 0)
+            dC = to_device(stored(c0, "N", ldc))
+            print(f"cfg {cfg} {ta}{tb} {m}x{n}x{k}", flush=True)
+            mg.gemm(ta, tb, m, n, k, 1.25, dA, lda, dB, ldb, -0.5, dC, ldc, dtype)
+            torch.cuda.synchronize()
+            assert mg.last_config()["cfg"] == cfg
+            outs[cfg] = dC.cpu().numpy()
+    finally:
+        mg.force_config(dtype, -1, 0)
+    for cfg in packed:
+        assert np.array_equal(outs[cfg], outs[0]), f"packed cfg {cfg} differs from fused"
 
 
 @pytest.mark.parametrize("dtype", ALL_DTYPES, ids=lambda d: mg.DTYPE_NAMES[d])
