@@ -171,10 +171,12 @@ def main():
                                "im2col shapes (50176,64,576) (3136,256,2304) (196,1024,4608) "
                                "(12544,128,1152); beta in {0,1}; alpha=1; row-major NN",
                    "gemms_per_step": len(SWEEP) * len(BETAS), "parallelism": "single GPU"},
-        "roofline": {"bound": "mfma", "kernel": "gemm_tile_kernel FP32 8192^3",
+        "roofline": {"bound": "mfma",
+                     "kernel": ("gemm_direct_kernel" if cfg.get("staging") == "direct"
+                                else "gemm_tile_kernel") + " FP32 8192^3",
                      "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                     "traffic": profile_traffic("fp32_gemm_tile_8192_sweep.md"),
+                     "traffic": profile_traffic("fp32_gemm_8192_sweep.md"),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, scaled)",
                      "avg_ms": round(dom_ms, 4), "tile": cfg},
     }

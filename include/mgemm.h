@@ -182,7 +182,15 @@ int gemm_last_hip_error(void);
  *   gemm_num_configs(dtype): number of compiled tile configurations.
  *   gemm_config_info(dtype, id, out[8]): out = {mc, nc, kc, wave tile m,
  *     wave tile n, threads, lds bytes, kind}; kind 0 = C resident in
- *     registers, 1 = A resident, 2 = B resident (paper section 4).
+ *     registers (B3A2C0 / A3B2C0), 1..4 = operand resident (B3C2A0, A3C2B0,
+ *     C3A2B0, C3B2A0; paper section 4), 5 = packed split product (split
+ *     dtypes: a packing pass writes the operands' bf16 pieces, then a bf16
+ *     tile multiplies them).
+ *   gemm_config_staging(dtype, id): how the configuration fills its LDS
+ *     panels: 0 = global loads through registers (converted, transposed and
+ *     stored by the workgroup), 1 = direct global -> LDS loads into a ring of
+ *     stages, 2 = packed split (packing pass, then a direct bf16 tile);
+ *     negative as gemm_config_info's errors.
  *   gemm_force_config(dtype, id, order): pin the next calls on this thread
  *     to configuration `id` with raster order `order` (0 = B3A2C0, column
  *     panels outer; 1 = A3B2C0, row panels outer); id < 0 clears the pin.
@@ -191,6 +199,7 @@ int gemm_last_hip_error(void);
  */
 int gemm_num_configs(int dtype);
 int gemm_config_info(int dtype, int id, int64_t out[8]);
+int gemm_config_staging(int dtype, int id);
 int gemm_force_config(int dtype, int id, int order);
 int gemm_last_config(int64_t out[4]);
 

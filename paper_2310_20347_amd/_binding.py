@@ -94,6 +94,8 @@ def lib():
     L.gemm_num_configs.restype = _INT
     L.gemm_config_info.argtypes = [_INT, _INT, ctypes.POINTER(_I64)]
     L.gemm_config_info.restype = _INT
+    L.gemm_config_staging.argtypes = [_INT, _INT]
+    L.gemm_config_staging.restype = _INT
     L.gemm_force_config.argtypes = [_INT, _INT, _INT]
     L.gemm_force_config.restype = _INT
     L.gemm_last_config.argtypes = [ctypes.POINTER(_I64)]
@@ -247,7 +249,10 @@ def config_info(dtype: int, cfg: int) -> dict:
     out = (_I64 * 8)()
     _check(lib().gemm_config_info(int(dtype), int(cfg), out), "gemm_config_info")
     keys = ("mc", "nc", "kc", "mr", "nr", "threads", "lds_bytes", "kind")
-    return dict(zip(keys, [int(v) for v in out]))
+    info = dict(zip(keys, [int(v) for v in out]))
+    st = int(lib().gemm_config_staging(int(dtype), int(cfg)))
+    info["staging"] = ("registers", "direct", "packed")[st] if st >= 0 else None
+    return info
 
 
 def force_config(dtype: int, cfg: int, order: int = 0) -> None:

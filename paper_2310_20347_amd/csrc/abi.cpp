@@ -628,6 +628,16 @@ int gemm_config_info(int dtype, int id, int64_t out[8])
     return GEMM_OK;
 }
 
+int gemm_config_staging(int dtype, int id)
+{
+    if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -1;
+    ensure_registered();
+    const std::vector<int> &ids = g_by_class[class_for_query(dtype)];
+    if (id < 0 || id >= (int)ids.size()) return -2;
+    const KernelCfg &c = g_cfgs[ids[id]];
+    return c.packed >= 0 ? 2 : (c.direct ? 1 : 0);
+}
+
 int gemm_force_config(int dtype, int id, int order)
 {
     if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -1;
