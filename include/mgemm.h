@@ -89,6 +89,9 @@ enum {
  *   dtype unknown; for GEMM_I8, alpha (-6) or beta (-11) not an int32 integer.
  *   The loop order, the block sizes (mc, nc, kc) and the MFMA wave tile are
  *   chosen per (dtype, trans, size bucket) from the tuning table (gemm_init).
+ *   Packed split and split-K configurations use a library-owned workspace
+ *   per stream that grows (allocates) when a call needs more than it holds;
+ *   if it cannot grow, the call runs an unsliced / fused configuration.
  */
 int gemm(char transA, char transB, int64_t m, int64_t n, int64_t k,
          double alpha, const void *A, int64_t lda, const void *B, int64_t ldb,
@@ -185,7 +188,11 @@ int gemm_last_hip_error(void);
  *     registers (B3A2C0 / A3B2C0), 1..4 = operand resident (B3C2A0, A3C2B0,
  *     C3A2B0, C3B2A0; paper section 4), 5 = packed split product (split
  *     dtypes: a packing pass writes the operands' bf16 pieces, then a bf16
- *     tile multiplies them).
+ *     tile multiplies them), 6 = split-K (the k loop is cut into slices of
+ *     whole stages run by separate workgroups, about two per CU, whose
+ *     partial tiles go to a per-stream workspace and are then summed in
+ *     slice order; deterministic, but float results differ in the last bits
+ *     from the unsliced order).
  *   gemm_config_staging(dtype, id): how the configuration fills its LDS
  *     panels: 0 = global loads through registers (converted, transposed and
  *     stored by the workgroup), 1 = direct global -> LDS loads into a ring of

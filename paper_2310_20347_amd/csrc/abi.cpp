@@ -139,9 +139,29 @@ void ensure_registered()
             p.direct = false;
             p.packed = (int)i;
             for (int t = 0; t < 4; ++t)
-                for (int v = 0; v < 2; ++v) p.func[t][v] = split_pack_entry();
+                for (int v = 0; v < 2; ++v) {
+                    p.func[t][v] = split_pack_entry();
+                    p.splitk[t][v] = nullptr;
+                }
             g_cfgs.push_back(p);
         }
+    }
+    // split-K: every tile compiled with a sliced form
+    const size_t nall = g_cfgs.size();
+    for (size_t i = 0; i < nall; ++i) {
+        const KernelCfg &b = g_cfgs[i];
+        bool any = false;
+        for (int t = 0; t < 4; ++t) any = any || b.splitk[t][0] || b.splitk[t][1];
+        if (!any) continue;
+        KernelCfg p = b;
+        p.kind = 6;
+        p.base = (int)i;
+        for (int t = 0; t < 4; ++t)
+            for (int v = 0; v < 2; ++v) {
+                p.func[t][v] = b.splitk[t][v];
+                p.splitk[t][v] = nullptr;
+            }
+        g_cfgs.push_back(p);
     }
     for (size_t i = 0; i < g_cfgs.size(); ++i) g_by_class[g_cfgs[i].kclass].push_back((int)i);
     g_registered = true;
@@ -431,9 +451,46 @@ static int launch_packed(const KernelCfg &c, int trans, const GemmArgs &a, hipSt
     return launch_gemm(g_cfgs[c.packed], 1, true, b, s);
 }
 
+// Split-K: S slices of k (each a whole number of stages, at least two)
+// chosen to give about two workgroups per CU, partial tiles in the stream's
+// workspace, then the ordered reduction.  One slice runs the plain tile.
+static int launch_splitk(const KernelCfg &c, int trans, bool vec, const GemmArgs &a, hipStream_t s)
+{
+    DevState *d = nullptr;
+    int rc = device_state(&d);
+    if (rc != GEMM_OK) return rc;
+    const int64_t tiles = int64_t(a.tiles_m) * a.tiles_n;
+    const int64_t nk = (int64_t(a.k) + c.kc - 1) / c.kc;
+    int64_t S = (2 * int64_t(d->cus) + tiles - 1) / tiles;
+    S = std::min<int64_t>(S, std::min<int64_t>(16, nk / 2));
+    const KernelCfg &b = g_cfgs[c.base];
+    if (S <= 1) return launch_gemm(b, trans, vec, a, s);
+    const int64_t kslice = (nk + S - 1) / S * c.kc;
+    S = (a.k + kslice - 1) / kslice;
+    const size_t bytes = size_t(S) * a.m * a.n * 4;
+    void *ws = stream_workspace(d, s, bytes);
+    if (!ws) return launch_gemm(b, trans, vec, a, s);
+    const void *f = c.func[trans][vec ? 1 : 0];
+    if (!f) return GEMM_E_UNSUPPORTED;
+    GemmArgs copy = a;
+    int ks = (int)kslice;
+    void *args[] = {&copy, &ks, &ws};
+    hipError_t e = hipLaunchKernel(f, dim3((unsigned)(tiles * S)), dim3(c.threads), args, 0, s);
+    if (e == hipSuccess) {
+        launch_splitk_reduce(ws, (int)S, a.C, a.ldc, a.m, a.n, a, c.kclass == K_I8, s);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) {
+        t_tls.hip_err = (int)e;
+        return GEMM_E_HIP;
+    }
+    return GEMM_OK;
+}
+
 int launch_gemm(const KernelCfg &c, int trans, bool vec, const GemmArgs &a, hipStream_t s)
 {
     if (c.packed >= 0) return launch_packed(c, trans, a, s);
+    if (c.base >= 0) return launch_splitk(c, trans, vec, a, s);
     const void *f = c.func[trans][vec ? 1 : 0];
     if (!f) return GEMM_E_UNSUPPORTED;
     const int64_t blocks = int64_t(a.tiles_m) * a.tiles_n;

@@ -9,17 +9,18 @@
 namespace mg {
 
 template <class DT, int MC, int NC, int WM, int WN, int ST, bool TA, bool TB, bool VEC, int PF,
-          bool PEEL>
+          bool PEEL, bool SPLITK = false>
 static void fill_one(KernelCfg &c)
 {
     typedef Tile<DT, MC, NC, WM, WN, TA, TB, VEC, ST, PF, PEEL> T;
     c.func[2 * TA + TB][VEC] = (const void *)&gemm_tile_kernel<T>;
+    if constexpr (SPLITK) c.splitk[2 * TA + TB][VEC] = (const void *)&gemm_splitk_kernel<T, DT::GES, TA, TB>;
 }
 
 // Adds configuration (MC, NC, WM, WN, ST) of dtype DT; the element-wise
 // (unaligned) staging variant is compiled only when WITH_SCALAR is set.
 template <class DT, int MC, int NC, int WM, int WN, int ST, bool WITH_SCALAR, int PF = 1,
-          bool PEEL = true>
+          bool PEEL = true, bool SPLITK = false>
 static void add_cfg(std::vector<KernelCfg> &out, int kclass)
 {
     typedef Tile<DT, MC, NC, WM, WN, false, false, true, ST, PF, PEEL> T;
@@ -34,15 +35,15 @@ static void add_cfg(std::vector<KernelCfg> &out, int kclass)
     c.lds = T::LDS_BYTES;
     c.stages = ST;
     c.kind = 0;
-    fill_one<DT, MC, NC, WM, WN, ST, false, false, true, PF, PEEL>(c);
-    fill_one<DT, MC, NC, WM, WN, ST, false, true, true, PF, PEEL>(c);
-    fill_one<DT, MC, NC, WM, WN, ST, true, false, true, PF, PEEL>(c);
-    fill_one<DT, MC, NC, WM, WN, ST, true, true, true, PF, PEEL>(c);
+    fill_one<DT, MC, NC, WM, WN, ST, false, false, true, PF, PEEL, SPLITK>(c);
+    fill_one<DT, MC, NC, WM, WN, ST, false, true, true, PF, PEEL, SPLITK>(c);
+    fill_one<DT, MC, NC, WM, WN, ST, true, false, true, PF, PEEL, SPLITK>(c);
+    fill_one<DT, MC, NC, WM, WN, ST, true, true, true, PF, PEEL, SPLITK>(c);
     if constexpr (WITH_SCALAR) {
-        fill_one<DT, MC, NC, WM, WN, ST, false, false, false, PF, PEEL>(c);
-        fill_one<DT, MC, NC, WM, WN, ST, false, true, false, PF, PEEL>(c);
-        fill_one<DT, MC, NC, WM, WN, ST, true, false, false, PF, PEEL>(c);
-        fill_one<DT, MC, NC, WM, WN, ST, true, true, false, PF, PEEL>(c);
+        fill_one<DT, MC, NC, WM, WN, ST, false, false, false, PF, PEEL, SPLITK>(c);
+        fill_one<DT, MC, NC, WM, WN, ST, false, true, false, PF, PEEL, SPLITK>(c);
+        fill_one<DT, MC, NC, WM, WN, ST, true, false, false, PF, PEEL, SPLITK>(c);
+        fill_one<DT, MC, NC, WM, WN, ST, true, true, false, PF, PEEL, SPLITK>(c);
     }
     out.push_back(c);
 }
@@ -92,14 +93,15 @@ static void add_resident_family(std::vector<KernelCfg> &out, int kclass)
 // Adds a direct-staged configuration (NS-deep LDS ring, direct.hpp): the
 // vectorised variant of all four transpositions; unaligned operands fall
 // back to the class's configuration 0.
-template <class DT, int MC, int NC, int WM, int WN, int NS, bool TA, bool TB>
+template <class DT, int MC, int NC, int WM, int WN, int NS, bool TA, bool TB, bool SPLITK>
 static void fill_direct(KernelCfg &c)
 {
     typedef DTile<DT, MC, NC, WM, WN, TA, TB, NS> T;
     c.func[2 * TA + TB][1] = (const void *)&gemm_direct_kernel<T>;
+    if constexpr (SPLITK) c.splitk[2 * TA + TB][1] = (const void *)&gemm_splitk_kernel<T, DT::GES, TA, TB>;
 }
 
-template <class DT, int MC, int NC, int WM, int WN, int NS>
+template <class DT, int MC, int NC, int WM, int WN, int NS, bool SPLITK = false>
 static void add_direct(std::vector<KernelCfg> &out, int kclass)
 {
     typedef DTile<DT, MC, NC, WM, WN, false, false, NS> T;
@@ -115,10 +117,10 @@ static void add_direct(std::vector<KernelCfg> &out, int kclass)
     c.stages = NS;
     c.kind = 0;
     c.direct = true;
-    fill_direct<DT, MC, NC, WM, WN, NS, false, false>(c);
-    fill_direct<DT, MC, NC, WM, WN, NS, false, true>(c);
-    fill_direct<DT, MC, NC, WM, WN, NS, true, false>(c);
-    fill_direct<DT, MC, NC, WM, WN, NS, true, true>(c);
+    fill_direct<DT, MC, NC, WM, WN, NS, false, false, SPLITK>(c);
+    fill_direct<DT, MC, NC, WM, WN, NS, false, true, SPLITK>(c);
+    fill_direct<DT, MC, NC, WM, WN, NS, true, false, SPLITK>(c);
+    fill_direct<DT, MC, NC, WM, WN, NS, true, true, SPLITK>(c);
     out.push_back(c);
 }
 

@@ -5,10 +5,10 @@
 namespace mg {
 void register_byte(std::vector<KernelCfg> &out)
 {
-    add_cfg<TF8, 64, 64, 2, 2, 2, true>(out, K_F8);
+    add_cfg<TF8, 64, 64, 2, 2, 2, true, 1, true, true>(out, K_F8);   // also split-K
     add_cfg<TF8, 128, 128, 2, 2, 2, false>(out, K_F8);
     add_cfg<TF8, 256, 128, 2, 2, 2, false>(out, K_F8);
-    add_cfg<TI8, 64, 64, 2, 2, 2, true>(out, K_I8);
+    add_cfg<TI8, 64, 64, 2, 2, 2, true, 1, true, true>(out, K_I8);   // also split-K
     add_cfg<TI8, 128, 128, 2, 2, 2, false>(out, K_I8);
     add_cfg<TI8, 256, 128, 2, 2, 2, false>(out, K_I8);
 }

@@ -9,7 +9,7 @@ static void add_half_direct(std::vector<KernelCfg> &out, int kclass)
     add_direct<DT, 256, 256, 2, 2, 2>(out, kclass);   // 4 waves of 128x128
     add_direct<DT, 256, 128, 2, 2, 3>(out, kclass);
     add_direct<DT, 128, 128, 2, 2, 4>(out, kclass);
-    add_direct<DT, 128, 128, 2, 2, 2>(out, kclass);   // two workgroups per CU
+    add_direct<DT, 128, 128, 2, 2, 2, true>(out, kclass);   // two workgroups per CU; also split-K
 }
 
 void register_direct_half(std::vector<KernelCfg> &out)

@@ -5,12 +5,12 @@
 namespace mg {
 void register_split(std::vector<KernelCfg> &out)
 {
-    add_cfg<TSplit<2>, 64, 64, 2, 2, 2, true>(out, K_SPLIT2);
+    add_cfg<TSplit<2>, 64, 64, 2, 2, 2, true, 1, true, true>(out, K_SPLIT2);   // also split-K
     add_cfg<TSplit<2>, 128, 128, 2, 2, 2, false>(out, K_SPLIT2);
     add_cfg<TSplit<2>, 128, 64, 2, 2, 2, false>(out, K_SPLIT2);
     add_cfg<TSplit<2>, 256, 128, 2, 2, 1, false>(out, K_SPLIT2);
     add_cfg<TSplit<2>, 128, 128, 2, 2, 2, false, 2>(out, K_SPLIT2);   // two stages in flight
-    add_cfg<TSplit<3>, 64, 64, 2, 2, 1, true>(out, K_SPLIT3);
+    add_cfg<TSplit<3>, 64, 64, 2, 2, 1, true, 1, true, true>(out, K_SPLIT3);   // also split-K
     add_cfg<TSplit<3>, 128, 128, 2, 2, 1, false>(out, K_SPLIT3);
 }
 }  // namespace mg

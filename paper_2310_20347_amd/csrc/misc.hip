@@ -1,5 +1,6 @@
 // Small auxiliary kernels: C = beta*C (the alpha == 0 / k == 0 case of the
-// BLAS semantics) and a deterministic operand fill used by the tuner.
+// BLAS semantics), the split-K reduction and a deterministic operand fill
+// used by the tuner.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -42,6 +43,55 @@ void launch_scale(void *C, int64_t ldc, int m, int n, double beta, bool is_int, 
     else
         hipLaunchKernelGGL(scale_f32_kernel, dim3((unsigned)blocks), dim3(threads), 0, s,
                            (float *)C, ldc, m, n, (float)beta);
+}
+
+// Split-K reduction: the S partial tiles (row stride n) summed in slice
+// order, then the BLAS epilogue.
+__global__ void splitk_reduce_f32(const float *P, int S, float *C, int64_t ldc, int m, int n,
+                                  float alpha, float beta)
+{
+    const int64_t total = (int64_t)m * n, slice = (int64_t)m * n;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        float acc = P[t];
+        for (int s = 1; s < S; ++s) acc += P[s * slice + t];
+        const int64_t i = t / n, j = t - i * n;
+        float *c = C + i * ldc + j;
+        float v = alpha * acc;
+        if (beta != 0.0f) v = __builtin_fmaf(beta, *c, v);
+        *c = v;
+    }
+}
+
+__global__ void splitk_reduce_i32(const int *P, int S, int *C, int64_t ldc, int m, int n, int alpha,
+                                  int beta)
+{
+    const int64_t total = (int64_t)m * n, slice = (int64_t)m * n;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        unsigned acc = (unsigned)P[t];
+        for (int s = 1; s < S; ++s) acc += (unsigned)P[s * slice + t];
+        const int64_t i = t / n, j = t - i * n;
+        int *c = C + i * ldc + j;
+        unsigned v = (unsigned)alpha * acc;
+        if (beta != 0) v += (unsigned)beta * (unsigned)*c;
+        *c = (int)v;
+    }
+}
+
+void launch_splitk_reduce(const void *P, int S, void *C, int64_t ldc, int m, int n,
+                          const GemmArgs &a, bool is_int, hipStream_t s)
+{
+    const int64_t total = (int64_t)m * n;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    if (is_int)
+        hipLaunchKernelGGL(splitk_reduce_i32, dim3((unsigned)blocks), dim3(256), 0, s,
+                           (const int *)P, S, (int *)C, ldc, m, n, a.ialpha, a.ibeta);
+    else
+        hipLaunchKernelGGL(splitk_reduce_f32, dim3((unsigned)blocks), dim3(256), 0, s,
+                           (const float *)P, S, (float *)C, ldc, m, n, a.alpha, a.beta);
 }
 
 __device__ __forceinline__ uint32_t mix(uint64_t x)

@@ -27,12 +27,17 @@ struct KernelCfg {
     int threads = 0;
     int lds = 0;            // bytes of LDS per workgroup
     int stages = 0;
-    int kind = 0;           // 0: C resident (registers); 1..4: operand resident; 5: packed split
+    int kind = 0;           // 0: C resident; 1..4: operand resident; 5: packed split; 6: split-K
     bool direct = false;    // stages fed by direct global -> LDS loads
     int packed = -1;        // packed split: registry index of the bf16 tile run on the packed operands
+    int base = -1;          // split-K: registry index of the tile it slices
     // kernel entry per [trans index = 2*transA + transB][vectorised staging]
     const void *func[4][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr},
                               {nullptr, nullptr}};
+    // split-K form of the same tile (k sliced over workgroups, partial tiles
+    // to a workspace, then an ordered reduction); null when not compiled
+    const void *splitk[4][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr},
+                                {nullptr, nullptr}};
 };
 
 // Each instantiation unit appends its configurations.
@@ -50,5 +55,10 @@ void register_direct_byte(std::vector<KernelCfg> &out);
 
 // Plain C = beta * C (alpha == 0 or k == 0), float or int32 elements.
 void launch_scale(void *C, int64_t ldc, int m, int n, double beta, bool is_int, hipStream_t s);
+
+// Split-K reduction: C = alpha * sum_{s < S} P[s] + beta * C, slices summed in
+// order (P: S partial m x n tiles, row stride n, float or int32).
+void launch_splitk_reduce(const void *P, int S, void *C, int64_t ldc, int m, int n,
+                          const GemmArgs &a, bool is_int, hipStream_t s);
 
 }  // namespace mg

@@ -622,6 +622,42 @@ struct Tile {
     }
 };
 
+// Split-K: workgroup b computes tile b % tiles over k slice b / tiles
+// (kslice values of k, a multiple of the stage depth so that operand
+// pointers keep their alignment) and writes the partial tile, unscaled, to
+// slice's m x n block of the workspace P; a separate reduction adds the
+// slices in order (the paper's "pc cannot be parallelised" race resolved by
+// an explicit, deterministic reduction).
+template <class T, int GES, bool TA, bool TB>
+__device__ __forceinline__ void run_slice(const GemmArgs &p, int kslice, void *P, char *lds)
+{
+    const int nblocks = p.tiles_m * p.tiles_n;
+    const int b = (int)blockIdx.x;
+    const int slice = b / nblocks;
+    const int t = xcd_remap(b - slice * nblocks, nblocks);
+    int tm, tn;
+    raster(t, p.tiles_m, p.tiles_n, p.order, p.group, tm, tn);
+    const int k0 = slice * kslice;
+    GemmArgs q = p;
+    q.k = min(kslice, p.k - k0);
+    q.A = (const char *)p.A + (TA ? (int64_t)k0 * p.lda : (int64_t)k0) * GES;
+    q.B = (const char *)p.B + (TB ? (int64_t)k0 : (int64_t)k0 * p.ldb) * GES;
+    q.C = (char *)P + (int64_t)slice * p.m * p.n * 4;
+    q.ldc = p.n;
+    q.alpha = 1.0f;
+    q.beta = 0.0f;
+    q.ialpha = 1;
+    q.ibeta = 0;
+    T::run(q, tm, tn, lds);
+}
+
+template <class T, int GES, bool TA, bool TB>
+__global__ void __launch_bounds__(T::NT, T::MINB) gemm_splitk_kernel(GemmArgs p, int kslice, void *P)
+{
+    __shared__ __attribute__((aligned(16))) char lds[T::LDS_BYTES];
+    run_slice<T, GES, TA, TB>(p, kslice, P, lds);
+}
+
 // One workgroup per tile.
 template <class T>
 __global__ void __launch_bounds__(T::NT, T::MINB) gemm_tile_kernel(GemmArgs p)

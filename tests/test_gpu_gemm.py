@@ -152,6 +152,34 @@ def test_packed_split_equals_fused_split_bitwise(dtype, ta, tb):
         assert np.array_equal(outs[cfg], outs[0]), f"packed cfg {cfg} differs from fused"
 
 
+@pytest.mark.parametrize("dtype", [mg.GEMM_F32, mg.GEMM_F32_BF16X3, mg.GEMM_BF16, mg.GEMM_F8E4M3,
+                                   mg.GEMM_I8], ids=lambda d: mg.DTYPE_NAMES[d])
+@pytest.mark.parametrize("ta,tb", [("N", "N"), ("T", "T")])
+def test_split_k_configurations_vs_oracle(dtype, ta, tb):
+    """Split-K (k cut into slices of whole stages, partial tiles summed in
+    order): the tall-k shape (196, 1024, 4608) of the sweep and a ragged one,
+    to the parity bar (INT8 bit-exact)."""
+    sk = [i for i in range(mg.num_configs(dtype)) if mg.config_info(dtype, i)["kind"] == 6]
+    assert sk, "no split-K configuration registered"
+    try:
+        for shape in [(196, 1024, 4608), (144, 80, 1008)]:   # 16-byte leading dimensions
+            m, n, k = shape
+            es = {mg.GEMM_BF16: 2, mg.GEMM_F8E4M3: 1, mg.GEMM_I8: 1}.get(dtype, 4)
+            lds = ((m if ta == "T" else k), (k if tb == "T" else n))
+            aligned = all(ld * es % 16 == 0 for ld in lds)
+            for cfg in sk:
+                mg.force_config(dtype, cfg, 0)
+                c = Case(dtype, ta, tb, *shape, *_ab(dtype), seed=13)
+                print(f"cfg {cfg} case {c}", flush=True)
+                r = run_case(c)
+                # direct-staged tiles need 16-byte rows; otherwise configuration 0 runs
+                direct = mg.config_info(dtype, cfg)["staging"] == "direct"
+                assert r["cfg"]["cfg"] == (cfg if aligned or not direct else 0)
+                check(c, r)
+    finally:
+        mg.force_config(dtype, -1, 0)
+
+
 @pytest.mark.parametrize("dtype", ALL_DTYPES, ids=lambda d: mg.DTYPE_NAMES[d])
 @pytest.mark.parametrize("ta,tb", TRANS)
 def test_identity_and_permutation_pins(dtype, ta, tb):
