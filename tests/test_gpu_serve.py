@@ -19,8 +19,14 @@ def alone(pools, md):
     m, n, k, dt = md["m"], md["n"], md["k"], md["dtype"]
     out_t = torch.int32 if dt == mg.GEMM_I8 else torch.float32
     C = torch.zeros((m, n), dtype=out_t, device="cuda")
-    mg.gemm("N", "N", m, n, k, 1, pools.ptr(dt, md["a_off"]), md["lda"],
-            pools.ptr(dt, md["b_off"]), md["ldb"], 0, C, n, dt)
+    # an unsliced configuration (not split-K): the serving launches run
+    # unsliced tiles, and every unsliced configuration sums k in one order
+    mg.force_config(dt, 1, 0)
+    try:
+        mg.gemm("N", "N", m, n, k, 1, pools.ptr(dt, md["a_off"]), md["lda"],
+                pools.ptr(dt, md["b_off"]), md["ldb"], 0, C, n, dt)
+    finally:
+        mg.force_config(dt, -1, 0)
     torch.cuda.synchronize()
     return C.cpu().numpy()
 
