@@ -393,6 +393,13 @@ void *stream_workspace(DevState *d, hipStream_t s, size_t bytes)
     std::lock_guard<std::mutex> g(d->ws_mu);
     std::pair<void *, size_t> &w = d->ws[s];
     if (w.second >= bytes) return w.first;
+    // never allocate, free or synchronise inside a graph capture: the caller
+    // then runs a configuration that needs no workspace
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
     if (w.first) {
         // earlier GEMMs on this stream may still read the old buffer
         (void)hipStreamSynchronize(s);

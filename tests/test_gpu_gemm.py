@@ -180,6 +180,59 @@ def test_split_k_configurations_vs_oracle(dtype, ta, tb):
         mg.force_config(dtype, -1, 0)
 
 
+@pytest.mark.parametrize("dtype,kind", [(mg.GEMM_F32, 6), (mg.GEMM_F32_BF16X3, 5),
+                                        (mg.GEMM_F32_BF16X3, 6)],
+                         ids=["f32-splitk", "bf16x3-packed", "bf16x3-splitk"])
+def test_workspace_configurations_under_graph_capture(dtype, kind):
+    """Configurations that use the per-stream workspace (packed split, split-K)
+    inside a captured HIP graph.  With the workspace grown before capture the
+    replays reproduce the eager result bit for bit (each replay checked, with
+    eager work in between); on a stream that has none the capture takes a
+    configuration that needs no workspace, allocating nothing, and the replay
+    still matches the oracle."""
+    import torch
+    from gemm_cases import stored
+    cfg = [i for i in range(mg.num_configs(dtype)) if mg.config_info(dtype, i)["kind"] == kind][0]
+    m, n, k = 196, 1024, 2304
+    c = Case(dtype, "N", "N", m, n, k, 1.0, 0.0, seed=14)
+    from gemm_cases import make_operands
+    a32, b32, _ = make_operands(c)
+    dA, dB = to_device(a32), to_device(b32)
+    dC = torch.zeros((m, n), dtype=torch.float32, device="cuda")
+    ref_q = oracle.gemm_f64("N", "N", m, n, k, 1.0, a32.astype(np.float64), k,
+                            b32.astype(np.float64), n)
+    try:
+        mg.force_config(dtype, cfg, 0)
+        s1 = torch.cuda.Stream()
+        mg.gemm("N", "N", m, n, k, 1.0, dA, k, dB, n, 0.0, dC, n, dtype, stream=s1)
+        torch.cuda.synchronize()
+        eager = dC.cpu().numpy().copy()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s1):
+            with torch.cuda.graph(g, stream=s1):
+                mg.gemm("N", "N", m, n, k, 1.0, dA, k, dB, n, 0.0, dC, n, dtype, stream=s1)
+        for rep in range(3):
+            dC.fill_(7.0)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert np.array_equal(dC.cpu().numpy(), eager), f"replay {rep} differs from eager"
+        s2 = torch.cuda.Stream()   # no workspace on this stream yet
+        g2 = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s2):
+            with torch.cuda.graph(g2, stream=s2):
+                mg.gemm("N", "N", m, n, k, 1.0, dA, k, dB, n, 0.0, dC, n, dtype, stream=s2)
+        dC.fill_(7.0)
+        torch.cuda.synchronize()
+        g2.replay()
+        torch.cuda.synchronize()
+        err = oracle.normalized_error(dC.cpu().numpy(), ref_q, k, float(np.abs(a32).max()),
+                                      float(np.abs(b32).max()))
+        assert err <= 2e-6, f"fallback capture error {err:.3g}"
+    finally:
+        mg.force_config(dtype, -1, 0)
+
+
 @pytest.mark.parametrize("dtype", ALL_DTYPES, ids=lambda d: mg.DTYPE_NAMES[d])
 @pytest.mark.parametrize("ta,tb", TRANS)
 def test_identity_and_permutation_pins(dtype, ta, tb):
