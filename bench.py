@@ -257,7 +257,40 @@ def extras(mg, torch, stream, ops):
     prec["i8"] = {"ms": round(ms, 3), "tops": round(2.0 * n ** 3 / ms / 1e9, 1),
                   "mfma_util": round(2.0 * n ** 3 / ms / 1e9 / 5033.0, 4)}
     res["precision_8192"] = prec
+    res["packing_configs"] = packing_configs(mg, torch, stream)
     return res
+
+
+def packing_configs(mg, torch, stream):
+    """The paper's packing experiment (section 8.6): FP32 'N','T' GEMMs with A
+    and B both staged in LDS, only B, only A, or neither (fragments loaded
+    straight into registers), 64x64 tiles, small and medium squares."""
+    out = {}
+    names = {"direct": "both_packed", "a_unpacked": "b_packed_only",
+             "b_unpacked": "a_packed_only", "unpacked": "none_packed"}
+    cfgs = {}
+    for i in range(mg.num_configs(mg.GEMM_F32)):
+        info = mg.config_info(mg.GEMM_F32, i)
+        if info["mc"] == 64 and info["nc"] == 64 and info["staging"] in names and \
+                info["kind"] == 0 and names[info["staging"]] not in cfgs:
+            cfgs[names[info["staging"]]] = i
+    # the register-staged 64x64 tile stands for "both packed" when no direct 64x64 exists
+    cfgs.setdefault("both_packed", 0)
+    for n in (256, 1024):
+        A = torch.rand((n, n), device="cuda") * 2 - 1
+        B = torch.rand((n, n), device="cuda") * 2 - 1
+        C = torch.empty((n, n), device="cuda")
+        row = {}
+        for name, cfg in sorted(cfgs.items()):
+            mg.force_config(mg.GEMM_F32, cfg, 0)
+            ms = _time_call(lambda: mg.gemm("N", "T", n, n, n, 1.0, A, n, B, n, 0.0, C, n,
+                                            mg.GEMM_F32, stream=stream), torch, stream, reps=10)
+            row[name] = {"cfg": cfg, "us": round(ms * 1e3, 2),
+                         "tflops": round(2.0 * n ** 3 / ms / 1e9, 2)}
+        mg.force_config(mg.GEMM_F32, -1, 0)
+        out[f"{n}^3"] = row
+        del A, B, C
+    return out
 
 
 def _dev_uniform(torch, shape, seed, dtype):

@@ -197,7 +197,15 @@ int gemm_last_hip_error(void);
  *     panels: 0 = global loads through registers (converted, transposed and
  *     stored by the workgroup), 1 = direct global -> LDS loads into a ring of
  *     stages, 2 = packed split (packing pass, then a direct bf16 tile);
- *     negative as gemm_config_info's errors.
+ *     packing configurations (paper section 5.3 / 8.6): 3 = A not packed
+ *     (its fragments go straight from global memory to registers; B through
+ *     LDS), 4 = B not packed, 5 = neither packed (no LDS); negative as
+ *     gemm_config_info's errors.
+ *   gemm_config_layouts(dtype, id): bit (2*t + v) is set when the
+ *     configuration has a kernel for trans index t = 2*(transA is T) +
+ *     (transB is T) with vectorised (v = 1: 16-byte aligned operands and
+ *     leading dimensions) or element-wise (v = 0) staging; for other
+ *     layouts a call forced to it runs the class's configuration 0.
  *   gemm_force_config(dtype, id, order): pin the next calls on this thread
  *     to configuration `id` with raster order `order` (0 = B3A2C0, column
  *     panels outer; 1 = A3B2C0, row panels outer); id < 0 clears the pin.
@@ -207,6 +215,7 @@ int gemm_last_hip_error(void);
 int gemm_num_configs(int dtype);
 int gemm_config_info(int dtype, int id, int64_t out[8]);
 int gemm_config_staging(int dtype, int id);
+int gemm_config_layouts(int dtype, int id);
 int gemm_force_config(int dtype, int id, int order);
 int gemm_last_config(int64_t out[4]);
 

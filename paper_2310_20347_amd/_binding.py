@@ -96,6 +96,8 @@ def lib():
     L.gemm_config_info.restype = _INT
     L.gemm_config_staging.argtypes = [_INT, _INT]
     L.gemm_config_staging.restype = _INT
+    L.gemm_config_layouts.argtypes = [_INT, _INT]
+    L.gemm_config_layouts.restype = _INT
     L.gemm_force_config.argtypes = [_INT, _INT, _INT]
     L.gemm_force_config.restype = _INT
     L.gemm_last_config.argtypes = [ctypes.POINTER(_I64)]
@@ -251,8 +253,16 @@ def config_info(dtype: int, cfg: int) -> dict:
     keys = ("mc", "nc", "kc", "mr", "nr", "threads", "lds_bytes", "kind")
     info = dict(zip(keys, [int(v) for v in out]))
     st = int(lib().gemm_config_staging(int(dtype), int(cfg)))
-    info["staging"] = ("registers", "direct", "packed")[st] if st >= 0 else None
+    info["staging"] = (("registers", "direct", "packed", "a_unpacked", "b_unpacked", "unpacked")[st]
+                       if st >= 0 else None)
+    info["layouts"] = int(lib().gemm_config_layouts(int(dtype), int(cfg)))
     return info
+
+
+def config_supports(dtype: int, cfg: int, transA: str, transB: str, vec: bool = True) -> bool:
+    """Whether configuration `cfg` has a kernel for this layout and staging."""
+    t = 2 * (transA in "TtCc") + (transB in "TtCc")
+    return bool(config_info(dtype, cfg)["layouts"] >> (2 * t + (1 if vec else 0)) & 1)
 
 
 def force_config(dtype: int, cfg: int, order: int = 0) -> None:

@@ -163,6 +163,8 @@ void ensure_registered()
             }
         g_cfgs.push_back(p);
     }
+    // packing configurations (A, B or neither through LDS)
+    register_nopack(g_cfgs);
     for (size_t i = 0; i < g_cfgs.size(); ++i) g_by_class[g_cfgs[i].kclass].push_back((int)i);
     g_registered = true;
 }
@@ -699,7 +701,22 @@ int gemm_config_staging(int dtype, int id)
     const std::vector<int> &ids = g_by_class[class_for_query(dtype)];
     if (id < 0 || id >= (int)ids.size()) return -2;
     const KernelCfg &c = g_cfgs[ids[id]];
+    if (c.unpacked) return 2 + c.unpacked;
     return c.packed >= 0 ? 2 : (c.direct ? 1 : 0);
+}
+
+int gemm_config_layouts(int dtype, int id)
+{
+    if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -1;
+    ensure_registered();
+    const std::vector<int> &ids = g_by_class[class_for_query(dtype)];
+    if (id < 0 || id >= (int)ids.size()) return -2;
+    const KernelCfg &c = g_cfgs[ids[id]];
+    int mask = 0;
+    for (int t = 0; t < 4; ++t)
+        for (int v = 0; v < 2; ++v)
+            if (c.func[t][v]) mask |= 1 << (2 * t + v);
+    return mask;
 }
 
 int gemm_force_config(int dtype, int id, int order)

@@ -38,8 +38,8 @@ typedef __attribute__((address_space(3))) char lds_char;
 typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
 typedef __attribute__((address_space(3))) i32x2 lds_i32x2;
 
-// Sixteen zero bytes: the source of every vector outside the operand.
-static __device__ __attribute__((aligned(16))) u32 g_zero_vec[4];
+// Thirty-two zero bytes: the source of every vector outside the operand.
+static __device__ __attribute__((aligned(16))) u32 g_zero_vec[8];
 
 // One direct global -> LDS load of 16 bytes per lane into the 1 KiB LDS
 // block at `lds_block` (M0 holds its LDS address).  Written as an asm

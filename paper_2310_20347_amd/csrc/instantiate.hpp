@@ -2,6 +2,7 @@
 #pragma once
 
 #include "direct.hpp"
+#include "nopack.hpp"
 #include "registry.hpp"
 #include "resident.hpp"
 #include "tile.hpp"
@@ -121,6 +122,43 @@ static void add_direct(std::vector<KernelCfg> &out, int kclass)
     fill_direct<DT, MC, NC, WM, WN, NS, false, true, SPLITK>(c);
     fill_direct<DT, MC, NC, WM, WN, NS, true, false, SPLITK>(c);
     fill_direct<DT, MC, NC, WM, WN, NS, true, true, SPLITK>(c);
+    out.push_back(c);
+}
+
+// Adds a packing configuration: A and/or B skip the LDS panel (nopack.hpp).
+// Only the layouts in which every unpacked operand is contiguous along k are
+// compiled (A unpacked: A 'N'; B unpacked: B 'T'); other layouts, and
+// unaligned operands, fall back to the class's configuration 0.
+template <class DT, int MC, int NC, int WM, int WN, bool PKA, bool PKB, bool TA, bool TB>
+static void fill_nopack(KernelCfg &c)
+{
+    if constexpr ((PKA || !TA) && (PKB || TB)) {
+        typedef UTile<DT, MC, NC, WM, WN, TA, TB, PKA, PKB> T;
+        c.func[2 * TA + TB][1] = (const void *)&gemm_nopack_kernel<T>;
+    }
+}
+
+template <class DT, int MC, int NC, int WM, int WN, bool PKA, bool PKB>
+static void add_nopack(std::vector<KernelCfg> &out, int kclass)
+{
+    typedef UTile<DT, MC, NC, WM, WN, false, true, PKA, PKB> T;
+    KernelCfg c;
+    c.kclass = kclass;
+    c.mc = MC;
+    c.nc = NC;
+    c.kc = T::KC;
+    c.wm = WM;
+    c.wn = WN;
+    c.threads = T::NT;
+    c.lds = T::LDS_BYTES;
+    c.stages = T::NS;
+    c.kind = 0;
+    c.direct = true;
+    c.unpacked = (PKA ? 0 : 1) | (PKB ? 0 : 2);
+    fill_nopack<DT, MC, NC, WM, WN, PKA, PKB, false, false>(c);
+    fill_nopack<DT, MC, NC, WM, WN, PKA, PKB, false, true>(c);
+    fill_nopack<DT, MC, NC, WM, WN, PKA, PKB, true, false>(c);
+    fill_nopack<DT, MC, NC, WM, WN, PKA, PKB, true, true>(c);
     out.push_back(c);
 }
 

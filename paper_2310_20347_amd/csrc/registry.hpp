@@ -31,6 +31,7 @@ struct KernelCfg {
     bool direct = false;    // stages fed by direct global -> LDS loads
     int packed = -1;        // packed split: registry index of the bf16 tile run on the packed operands
     int base = -1;          // split-K: registry index of the tile it slices
+    int unpacked = 0;       // packing configuration: bit 0 A, bit 1 B loaded straight to registers
     // kernel entry per [trans index = 2*transA + transB][vectorised staging]
     const void *func[4][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr},
                               {nullptr, nullptr}};
@@ -52,6 +53,7 @@ void register_resident_byte(std::vector<KernelCfg> &out);
 void register_direct_f32(std::vector<KernelCfg> &out);
 void register_direct_half(std::vector<KernelCfg> &out);
 void register_direct_byte(std::vector<KernelCfg> &out);
+void register_nopack(std::vector<KernelCfg> &out);
 
 // Plain C = beta * C (alpha == 0 or k == 0), float or int32 elements.
 void launch_scale(void *C, int64_t ldc, int m, int n, double beta, bool is_int, hipStream_t s);

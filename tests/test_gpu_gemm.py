@@ -57,7 +57,9 @@ def test_every_configuration_and_raster_order(dtype):
                 c = Case(dtype, "N", "N", 300, 272, 288, 1.0, 1.0, dist="ints", seed=9)
                 print(f"cfg {cfg} order {order} case {c}", flush=True)
                 r = run_case(c)
-                assert r["cfg"]["cfg"] == cfg and r["cfg"]["order"] == order
+                # a configuration without an 'N','N' kernel runs configuration 0
+                expect = cfg if mg.config_supports(dtype, cfg, "N", "N") else 0
+                assert r["cfg"]["cfg"] == expect and r["cfg"]["order"] == order
                 check(c, r)
                 ref = r["Cq"] if r.get("Cq") is not None else r["Cs"]
                 assert np.array_equal(r["C"], np.asarray(ref).astype(r["C"].dtype)), \
@@ -111,7 +113,8 @@ def test_every_configuration_every_layout_ragged(dtype):
                     print(f"cfg {cfg} {ta}{tb} {m}x{n}x{k}", flush=True)
                     mg.gemm(ta, tb, m, n, k, 1.0, dA, lda, dB, ldb, -1.0, dC, ldc, dtype)
                     torch.cuda.synchronize()
-                    assert mg.last_config()["cfg"] == cfg
+                    expect = cfg if mg.config_supports(fam, cfg, ta, tb) else 0
+                    assert mg.last_config()["cfg"] == expect
                     C = dC.cpu().numpy().reshape(m, ldc)[:, :n]
                     assert np.array_equal(C, np.asarray(ref).astype(C.dtype)), \
                         f"cfg {cfg} {ta}{tb} {m}x{n}x{k} not exact"
@@ -229,6 +232,34 @@ def test_workspace_configurations_under_graph_capture(dtype, kind):
         err = oracle.normalized_error(dC.cpu().numpy(), ref_q, k, float(np.abs(a32).max()),
                                       float(np.abs(b32).max()))
         assert err <= 2e-6, f"fallback capture error {err:.3g}"
+    finally:
+        mg.force_config(dtype, -1, 0)
+
+
+@pytest.mark.parametrize("dtype", [mg.GEMM_F32, mg.GEMM_BF16], ids=lambda d: mg.DTYPE_NAMES[d])
+def test_packing_configurations_vs_oracle(dtype):
+    """Packing configurations (A, B or neither staged in LDS; the others'
+    fragments loaded straight into registers) in every layout they support,
+    on shapes ragged against the tile, the fragment vector and the stage."""
+    cfgs = [i for i in range(mg.num_configs(dtype))
+            if mg.config_info(dtype, i)["staging"] in ("a_unpacked", "b_unpacked", "unpacked")]
+    assert len(cfgs) >= 3, "packing configurations missing"
+    try:
+        for cfg in cfgs:
+            for ta, tb in TRANS:
+                if not mg.config_supports(dtype, cfg, ta, tb):
+                    continue
+                for shape in [(64, 64, 64), (100, 200, 296), (257, 136, 1000)]:
+                    mg.force_config(dtype, cfg, 0)
+                    c = Case(dtype, ta, tb, *shape, *_ab(dtype), dist="normal", seed=15)
+                    print(f"cfg {cfg} case {c}", flush=True)
+                    r = run_case(c)
+                    m, n, k = shape
+                    es = 4 if dtype == mg.GEMM_F32 else 2
+                    lds = ((m if ta == "T" else k), (k if tb == "T" else n))
+                    aligned = all(ld * es % 16 == 0 for ld in lds)
+                    assert r["cfg"]["cfg"] == (cfg if aligned else 0)
+                    check(c, r)
     finally:
         mg.force_config(dtype, -1, 0)
 
