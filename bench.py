@@ -37,6 +37,8 @@ def parse():
     p.add_argument("--no-extras", action="store_true")
     p.add_argument("--profile-only", action="store_true",
                    help="only the timed steps (for rocprofv3 runs)")
+    p.add_argument("--profile-precision", action="store_true",
+                   help="only the 8192^3 GEMM of every precision path (for rocprofv3 runs)")
     p.add_argument("--calib-copy", action="store_true",
                    help="copy a 1 GiB buffer once before the steps: a kernel of known HBM "
                         "traffic to scale rocprofv3's FETCH_SIZE / WRITE_SIZE counters")
@@ -112,6 +114,9 @@ def main():
     torch.cuda.set_device(0)
     mg.gemm_init(None)
     stream = torch.cuda.current_stream()
+    if args.profile_precision:
+        print(json.dumps({"precision_8192": precision_8192(mg, torch, stream)}), flush=True)
+        return
 
     # operands, resident in HBM before timing
     ops = []
@@ -224,6 +229,14 @@ def extras(mg, torch, stream, ops):
     res["sweep_beta0"] = {"f32_tflops": round(flops / tot_f32 / 1e9, 2),
                           "bf16x3_tflops": round(flops / tot_x3 / 1e9, 2),
                           "bf16x3_speedup_vs_f32": round(tot_f32 / tot_x3, 3)}
+    res["precision_8192"] = precision_8192(mg, torch, stream)
+    res["packing_configs"] = packing_configs(mg, torch, stream)
+    return res
+
+
+def precision_8192(mg, torch, stream):
+    """8192^3 in every precision path, N(0,1) inputs (INT8 uniform)."""
+    from paper_2310_20347_amd import inputs
     n = 8192
     a32 = inputs.normal((n, n), inputs.seed_for(3, "A"))
     b32 = inputs.normal((n, n), inputs.seed_for(3, "B"))
@@ -256,9 +269,7 @@ def extras(mg, torch, stream, ops):
                                     stream=stream), torch, stream)
     prec["i8"] = {"ms": round(ms, 3), "tops": round(2.0 * n ** 3 / ms / 1e9, 1),
                   "mfma_util": round(2.0 * n ** 3 / ms / 1e9 / 5033.0, 4)}
-    res["precision_8192"] = prec
-    res["packing_configs"] = packing_configs(mg, torch, stream)
-    return res
+    return prec
 
 
 def packing_configs(mg, torch, stream):
