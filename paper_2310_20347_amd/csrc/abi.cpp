@@ -165,6 +165,8 @@ void ensure_registered()
     }
     // packing configurations (A, B or neither through LDS)
     register_nopack(g_cfgs);
+    // split product on direct-staged FP32 panels
+    register_splitdirect(g_cfgs);
     for (size_t i = 0; i < g_cfgs.size(); ++i) g_by_class[g_cfgs[i].kclass].push_back((int)i);
     g_registered = true;
 }

@@ -66,24 +66,28 @@ __device__ __forceinline__ void wait_vm()
 
 // Chunk swizzle of an m/n-contiguous panel row kr: the rows read together by
 // one 16-lane group of a transposing read land on distinct banks.
-template <int GES>
+// SK selects the read pattern: 4, 2, 1 = the FP32, 16-bit and 8-bit MFMA
+// fragments; 8 = FP32 read for the split product (a 16-lane group reads 64
+// contiguous bytes of row 8g+e, so groups g and g+1 differ by 8 rows).
+template <int SK>
 __device__ __forceinline__ int mn_swz(int kr)
 {
-    return GES == 4 ? 4 * ((kr >> 2) & 1) : (GES == 2 ? 2 * (kr & 3) : (kr & 7));
+    return SK == 8 ? 4 * ((kr >> 3) & 1)
+                   : (SK == 4 ? 4 * ((kr >> 2) & 1) : (SK == 2 ? 2 * (kr & 3) : (kr & 7)));
 }
 
-template <int GES>
+template <int SK>
 __device__ __forceinline__ int mn_off(int kr, int row_bytes, int byte)
 {
     const int lc = byte >> 4;
-    return kr * row_bytes + (((lc & ~7) | ((lc ^ mn_swz<GES>(kr)) & 7)) << 4) + (byte & 15);
+    return kr * row_bytes + (((lc & ~7) | ((lc ^ mn_swz<SK>(kr)) & 7)) << 4) + (byte & 15);
 }
 
 // ---------------------------------------------------------------------------
 // One operand panel of a stage: ROWS rows of m (or n) x KC values of k,
 // ROWS/8 blocks of 1 KiB, PER blocks loaded by each of NW waves.
 // ---------------------------------------------------------------------------
-template <class DT, int ROWS, int NW, bool KMODE>
+template <class DT, int ROWS, int NW, bool KMODE, int SK = DT::GES>
 struct DPanel {
     static constexpr int GES = DT::GES, KC = 128 / GES, VK = 16 / GES;
     static constexpr int NB = ROWS / 8;         // 1 KiB blocks per panel
@@ -109,7 +113,7 @@ struct DPanel {
                 lim[q] = grow < R ? K - kof : INT_MIN;
             } else {
                 const int kr = (64 / CPR) * b + lane / CPR, pc = lane % CPR;
-                const int lc = (pc & ~7) | ((pc ^ mn_swz<GES>(kr)) & 7);
+                const int lc = (pc & ~7) | ((pc ^ mn_swz<SK>(kr)) & 7);
                 const int gcol = row0 + lc * VK;
                 off[q] = ((int64_t)kr * ld + gcol) * GES;
                 lim[q] = gcol < R ? K - kr : INT_MIN;

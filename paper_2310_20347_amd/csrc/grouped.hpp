@@ -11,6 +11,7 @@
 #pragma once
 
 #include "direct.hpp"
+#include "splitdirect.hpp"
 #include "tile.hpp"
 
 namespace mg {
@@ -51,6 +52,18 @@ struct DShape {
     typedef DT dt;
     static constexpr int mc = MC, nc = NC;
     typedef DTile<DT, MC, NC, 2, 2, false, false, NS> NN;
+    static constexpr int lds = NN::LDS_BYTES;
+    static __device__ __forceinline__ void run(const GemmArgs &p, int tm, int tn, char *l)
+    {
+        NN::run(p, tm, tn, l);
+    }
+};
+// A split-product 'N','N' tile shape on direct-staged FP32 panels.
+template <int P, int MC, int NC, int NS>
+struct SDShape {
+    typedef TSplit<P> dt;
+    static constexpr int mc = MC, nc = NC;
+    typedef SDTile<P, MC, NC, 2, 2, false, false, NS> NN;
     static constexpr int lds = NN::LDS_BYTES;
     static __device__ __forceinline__ void run(const GemmArgs &p, int tm, int tn, char *l)
     {

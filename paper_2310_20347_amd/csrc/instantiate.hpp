@@ -3,6 +3,7 @@
 
 #include "direct.hpp"
 #include "nopack.hpp"
+#include "splitdirect.hpp"
 #include "registry.hpp"
 #include "resident.hpp"
 #include "tile.hpp"
@@ -159,6 +160,38 @@ static void add_nopack(std::vector<KernelCfg> &out, int kclass)
     fill_nopack<DT, MC, NC, WM, WN, PKA, PKB, false, true>(c);
     fill_nopack<DT, MC, NC, WM, WN, PKA, PKB, true, false>(c);
     fill_nopack<DT, MC, NC, WM, WN, PKA, PKB, true, true>(c);
+    out.push_back(c);
+}
+
+// Adds a split-product configuration on direct-staged FP32 panels (the
+// pieces formed as fragments are read, splitdirect.hpp).
+template <int P, int MC, int NC, int WM, int WN, int NS, bool TA, bool TB>
+static void fill_splitdirect(KernelCfg &c)
+{
+    typedef SDTile<P, MC, NC, WM, WN, TA, TB, NS> T;
+    c.func[2 * TA + TB][1] = (const void *)&gemm_direct_kernel<T>;
+}
+
+template <int P, int MC, int NC, int WM, int WN, int NS>
+static void add_splitdirect(std::vector<KernelCfg> &out, int kclass)
+{
+    typedef SDTile<P, MC, NC, WM, WN, false, false, NS> T;
+    KernelCfg c;
+    c.kclass = kclass;
+    c.mc = MC;
+    c.nc = NC;
+    c.kc = T::KC;
+    c.wm = WM;
+    c.wn = WN;
+    c.threads = T::NT;
+    c.lds = T::LDS_BYTES;
+    c.stages = NS;
+    c.kind = 0;
+    c.direct = true;
+    fill_splitdirect<P, MC, NC, WM, WN, NS, false, false>(c);
+    fill_splitdirect<P, MC, NC, WM, WN, NS, false, true>(c);
+    fill_splitdirect<P, MC, NC, WM, WN, NS, true, false>(c);
+    fill_splitdirect<P, MC, NC, WM, WN, NS, true, true>(c);
     out.push_back(c);
 }
 

@@ -54,6 +54,7 @@ void register_direct_f32(std::vector<KernelCfg> &out);
 void register_direct_half(std::vector<KernelCfg> &out);
 void register_direct_byte(std::vector<KernelCfg> &out);
 void register_nopack(std::vector<KernelCfg> &out);
+void register_splitdirect(std::vector<KernelCfg> &out);
 
 // Plain C = beta * C (alpha == 0 or k == 0), float or int32 elements.
 void launch_scale(void *C, int64_t ldc, int m, int n, double beta, bool is_int, hipStream_t s);

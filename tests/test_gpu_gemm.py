@@ -131,7 +131,7 @@ def test_packed_split_equals_fused_split_bitwise(dtype, ta, tb):
     as the fused split tile: equal bits, on normal inputs with ragged k."""
     import torch
     from gemm_cases import encode, make_operands, stored
-    m, n, k = 200, 300, 515
+    m, n, k = 200, 304, 520   # 16-byte rows in every layout; k ragged against 32 and 64
     c = Case(dtype, ta, tb, m, n, k, 1.25, -0.5, dist="normal", seed=12)
     a32, b32, c0 = make_operands(c)
     lda, ldb, ldc = (m if ta == "T" else k), (k if tb == "T" else n), n
@@ -139,6 +139,10 @@ def test_packed_split_equals_fused_split_bitwise(dtype, ta, tb):
     dB = to_device(stored(encode(b32, dtype), tb, ldb))
     packed = [i for i in range(mg.num_configs(dtype)) if mg.config_info(dtype, i)["kind"] == 5]
     assert packed, "no packed split configuration registered"
+    # the split on direct-staged FP32 panels forms the same pieces as it reads
+    packed += [i for i in range(mg.num_configs(dtype))
+               if mg.config_info(dtype, i)["staging"] == "direct"
+               and mg.config_supports(dtype, i, ta, tb)]
     outs = {}
     try:
         for cfg in [0] + packed:   # configuration 0 also takes unaligned operands
