@@ -10,13 +10,16 @@
 // fp16, fp8, int8).  The XOR swizzle of the panels is applied on the global side:
 // each lane fetches the vector that belongs at the LDS slot it writes.
 //
-// Panel layouts (one stage, kc = 128 bytes of k per panel row):
-//   k-contiguous operand (A 'N', B 'T'): rows of m (or n), 128 bytes each,
-//     16-byte chunks swizzled as in the register-staged tile; fragments are
-//     read with ds_read_b128.
+// Panel layouts (one stage, KB = 128 or 64 bytes of k per panel row):
+//   k-contiguous operand (A 'N', B 'T'): rows of m (or n), KB bytes each,
+//     16-byte chunks swizzled (kslot); fragments are read with ds_read_b128.
 //   m/n-contiguous operand (A 'T', B 'N'): kc rows of k, each holding the
-//     panel's m (or n) values; fragments are read with the gfx950 transposing
-//     LDS reads (ds_read_b64_tr_b16 / _b8; lane mapping at read_frag_tr).
+//     panel's m (or n) values, chunks swizzled (mn_chunk); fragments are read
+//     with the gfx950 transposing LDS reads (ds_read_b64_tr_b16 / _b8; lane
+//     mapping at read_frag_tr).
+// 64-byte stages halve the LDS of a stage, so the same LDS holds a ring
+// twice as deep: more loads in flight for the MFMA-dense 16- and 8-bit
+// types, whose 128-byte stage is consumed in about a microsecond.
 //
 // Edges: a lane whose vector lies wholly outside the operand reads a zero
 // vector instead; a vector that starts inside and ends outside is read whole
@@ -64,36 +67,111 @@ __device__ __forceinline__ void wait_vm()
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-// Chunk swizzle of an m/n-contiguous panel row kr: the rows read together by
-// one 16-lane group of a transposing read land on distinct banks.
-// SK selects the read pattern: 4, 2, 1 = the FP32, 16-bit and 8-bit MFMA
-// fragments; 8 = FP32 read for the split product (a 16-lane group reads 64
-// contiguous bytes of row 8g+e, so groups g and g+1 differ by 8 rows).
-template <int SK>
-__device__ __forceinline__ int mn_swz(int kr)
+// Chunk swizzle of an m/n-contiguous panel: the physical 16-byte chunk of
+// logical chunk lc in k row kr (RB-byte rows).  gfx950's LDS has 64 banks
+// (256 bytes per line).  A 32-bit read serves 32 lanes per pass; a
+// transposing 64-bit read serves two 16-lane groups per pass, so the rows
+// read by lane groups g and g+1 must fill the two 128-byte halves of a bank
+// line without overlap (measured: with only the 16-lane groups spread, half
+// of the LDS cycles of those reads were bank conflicts).
+//   SK 4: FP32 MFMA fragment, 32-bit reads; group g reads 64 bytes of row 4g+d.
+//   SK 8: FP32 read of the split product; group g reads 64 bytes of row 8g+e.
+//   SK 2: 16-bit transposing read; group g reads 4 rows (8g + 4h + 0..3) of
+//         32 bytes, groups GS = 8 rows apart.
+//   SK 1: 8-bit transposing read; group g reads 8 rows (GS*g + 8h + 0..7) of
+//         16 bytes, groups GS = KF/4 rows apart.
+// Rows of 256 bytes or more start on a bank line, so the 128-byte half is
+// chunk bit 3 and the swizzle may flip it; 128-byte rows share a line with
+// their neighbour (row parity picks the half) and are spread within it.
+template <int SK, int RB, int GS>
+__device__ __forceinline__ int mn_chunk(int kr, int lc)
 {
-    return SK == 8 ? 4 * ((kr >> 3) & 1)
-                   : (SK == 4 ? 4 * ((kr >> 2) & 1) : (SK == 2 ? 2 * (kr & 3) : (kr & 7)));
+    static_assert((GS & (GS - 1)) == 0 && RB >= 128, "power-of-two group stride, rows >= 128 B");
+    int x, mask = 7;
+    if constexpr (SK == 8) {
+        x = 4 * ((kr >> 3) & 1);
+    } else if constexpr (SK == 4) {
+        x = 4 * ((kr >> 2) & 1);
+    } else if constexpr (SK == 2) {
+        if constexpr (RB >= 256) {
+            x = 2 * (kr & 3) | 8 * ((kr / GS) & 1);
+            mask = 15;
+        } else {
+            x = 2 * (((kr >> 1) & 1) | (((kr / GS) & 1) << 1));
+        }
+    } else {
+        if constexpr (RB >= 256) {
+            x = (kr & 7) | 8 * ((kr / GS) & 1);
+            mask = 15;
+        } else {
+            x = ((kr >> 1) & 3) | (((kr / GS) & 1) << 2);
+        }
+    }
+    return (lc & ~mask) | ((lc ^ x) & mask);
 }
 
-template <int SK>
-__device__ __forceinline__ int mn_off(int kr, int row_bytes, int byte)
+template <int SK, int RB, int GS>
+__device__ __forceinline__ int mn_off(int kr, int byte)
 {
-    const int lc = byte >> 4;
-    return kr * row_bytes + (((lc & ~7) | ((lc ^ mn_swz<SK>(kr)) & 7)) << 4) + (byte & 15);
+    return kr * RB + (mn_chunk<SK, RB, GS>(kr, byte >> 4) << 4) + (byte & 15);
+}
+
+// Chunk swizzle of a k-contiguous panel with KB-byte rows (KB = 128: 8
+// chunks; 64: 4 chunks): physical slot of logical chunk lc in row r.  A
+// 128-bit read serves 16 lanes per pass, rows r0..r0+7 of two lane groups
+// whose logical chunks differ by 1 (16- and 32-bit and INT8 fragments) or 2
+// (FP8 fragments, the split product's 32-byte reads).
+//   KB 128: two rows per 256-byte bank line, so the four even rows of a
+//     pass share one half line.  Their swizzles are {0, 3, 5, 6} (odd rows:
+//     {1, 2, 4, 7}); either set XOR 1 or 2 is the other set, so the two
+//     groups' chunks fill the half line exactly once.
+//   KB 64: four rows per line, rows r and r+4 share a quarter line; their
+//     swizzles differ by 3, so {c, c^3, c^1, c^2} (or c^2, c^1) are distinct.
+template <int KB>
+__device__ __forceinline__ int kslot(int r, int lc)
+{
+    if constexpr (KB == 128)
+        return lc ^ ((r & 7) ^ (((r >> 1) ^ (r >> 2)) & 1));
+    else
+        return lc ^ (3 * ((r >> 2) & 1));
+}
+
+template <int KB>
+__device__ __forceinline__ int k_off(int row, int byte)
+{
+    return row * KB + (kslot<KB>(row, byte >> 4) << 4) + (byte & 15);
+}
+
+// Fragment of the 16-row block at panel row r0 and chunk c of a k-contiguous
+// panel: lane l holds row r0 + l%16, k = c*KF + (l/16)*KF/4 .. +KF/4-1.
+template <class DT, int KB>
+__device__ __forceinline__ void read_frag_k(const char *panel, int r0, int c, int lane,
+                                            u32 (*f)[DT::FDW])
+{
+    const int r = r0 + (lane & 15);
+    const int byte = c * (DT::KF * DT::LES) + (lane >> 4) * (DT::FDW * 4);
+#pragma unroll
+    for (int h = 0; h < DT::FDW / 4; ++h) {
+        const u32x4 v = *(const u32x4 *)(panel + k_off<KB>(r, byte + 16 * h));
+#pragma unroll
+        for (int d = 0; d < 4; ++d) f[0][4 * h + d] = v[d];
+    }
 }
 
 // ---------------------------------------------------------------------------
-// One operand panel of a stage: ROWS rows of m (or n) x KC values of k,
-// ROWS/8 blocks of 1 KiB, PER blocks loaded by each of NW waves.
+// One operand panel of a stage: ROWS rows of m (or n) x KC values of k
+// (KB bytes of k per row), ROWS*KB/1024 blocks of 1 KiB, PER blocks loaded
+// by each of NW waves.
 // ---------------------------------------------------------------------------
-template <class DT, int ROWS, int NW, bool KMODE, int SK = DT::GES>
+template <class DT, int ROWS, int NW, bool KMODE, int SK = DT::GES, int KB = 128>
 struct DPanel {
-    static constexpr int GES = DT::GES, KC = 128 / GES, VK = 16 / GES;
-    static constexpr int NB = ROWS / 8;         // 1 KiB blocks per panel
+    static constexpr int GES = DT::GES, KC = KB / GES, VK = 16 / GES;
+    static constexpr int NB = ROWS * KB / 1024; // 1 KiB blocks per panel
+    static constexpr int CPK = KB / 16;         // k mode: chunks per row
     static constexpr int PER = NB / NW;         // blocks per wave
     static constexpr int RB = ROWS * GES;       // m/n mode: bytes per k row
     static constexpr int CPR = RB / 16;         // m/n mode: chunks per k row
+    static constexpr int GS = GES == 1 ? DT::KF / 4 : 8;   // m/n mode: rows between lane groups
     static_assert(NB % NW == 0, "panel blocks must divide among the waves");
     static_assert(KMODE || (RB >= 128 && 64 % CPR == 0), "m/n panel rows of 128..1024 bytes");
 
@@ -106,14 +184,14 @@ struct DPanel {
         for (int q = 0; q < PER; ++q) {
             const int b = wave * PER + q;
             if constexpr (KMODE) {
-                const int r = 8 * b + (lane >> 3);
-                const int lc = (lane & 7) ^ swz<4>(r);
+                const int r = (64 / CPK) * b + lane / CPK;
+                const int lc = kslot<KB>(r, lane % CPK);
                 const int grow = row0 + r, kof = lc * VK;
                 off[q] = ((int64_t)grow * ld + kof) * GES;
                 lim[q] = grow < R ? K - kof : INT_MIN;
             } else {
                 const int kr = (64 / CPR) * b + lane / CPR, pc = lane % CPR;
-                const int lc = (pc & ~7) | ((pc ^ mn_swz<SK>(kr)) & 7);
+                const int lc = mn_chunk<SK, RB, GS>(kr, pc);
                 const int gcol = row0 + lc * VK;
                 off[q] = ((int64_t)kr * ld + gcol) * GES;
                 lim[q] = gcol < R ? K - kr : INT_MIN;
@@ -140,7 +218,7 @@ struct DPanel {
         const int lc = valid_k / VK;
         const int keep = (valid_k % VK) * GES;   // bytes of the chunk to keep, 1..15
         for (int r = tid; r < ROWS; r += nt) {
-            u32x4 *p = (u32x4 *)(panel + lds_off<4>(r, lc * 16));
+            u32x4 *p = (u32x4 *)(panel + k_off<KB>(r, lc * 16));
             u32x4 v = *p;
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
@@ -174,7 +252,7 @@ __device__ __forceinline__ void read_frag_tr(const char *panel, int r0, int c, i
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
             const int kr = c * DT::KF + 4 * g + d;
-            f[0][d] = *(const u32 *)(panel + mn_off<4>(kr, RB, (r0 + s) * 4));
+            f[0][d] = *(const u32 *)(panel + mn_off<4, RB, 8>(kr, (r0 + s) * 4));
         }
     } else if constexpr (GES == 2) {
         // two reads of 4 k values: lane s addresses k row 4h + s/4, elements 4*(s%4)..+3
@@ -183,7 +261,7 @@ __device__ __forceinline__ void read_frag_tr(const char *panel, int r0, int c, i
             const int kr = c * DT::KF + 8 * g + 4 * h + (s >> 2);
             const int byte = (r0 + 4 * (s & 3)) * 2;
             const i16x4 v =
-                __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)(panel + mn_off<2>(kr, RB, byte)));
+                __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)(panel + mn_off<2, RB, 8>(kr, byte)));
             const u32x2 w = __builtin_bit_cast(u32x2, v);
             f[0][2 * h] = w[0];
             f[0][2 * h + 1] = w[1];
@@ -195,7 +273,7 @@ __device__ __forceinline__ void read_frag_tr(const char *panel, int r0, int c, i
             const int kr = c * DT::KF + (DT::KF / 4) * g + 8 * h + (s >> 1);
             const int byte = r0 + 8 * (s & 1);
             const i32x2 v =
-                __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_i32x2 *)(panel + mn_off<1>(kr, RB, byte)));
+                __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_i32x2 *)(panel + mn_off<1, RB, DT::KF / 4>(kr, byte)));
             f[0][2 * h] = (u32)v[0];
             f[0][2 * h + 1] = (u32)v[1];
         }
@@ -207,19 +285,20 @@ __device__ __forceinline__ void read_frag_tr(const char *panel, int r0, int c, i
 // with an NS-deep ring of LDS stages.  Requires 16-byte aligned operands and
 // leading dimensions (the vectorised case).
 // ---------------------------------------------------------------------------
-template <class DT, int MC, int NC, int WM, int WN, bool TA, bool TB, int NS>
+template <class DT, int MC, int NC, int WM, int WN, bool TA, bool TB, int NS, int KB = 128>
 struct DTile {
     static constexpr int NW = WM * WN, NT = 64 * NW;
-    static constexpr int KC = 128 / DT::GES;
+    static constexpr int KC = KB / DT::GES;
     static constexpr int WTM = MC / WM, WTN = NC / WN;
     static constexpr int FM = WTM / 16, FN = WTN / 16;
-    static constexpr int PANEL_A = MC * 128, PANEL_B = NC * 128;
+    static constexpr int PANEL_A = MC * KB, PANEL_B = NC * KB;
     static constexpr int STAGE_BYTES = PANEL_A + PANEL_B;
     static constexpr int LDS_BYTES = NS * STAGE_BYTES;
     static constexpr int MINB = 1;
     static constexpr int NCH = KC / DT::KF;   // fragment chunks per stage
-    typedef DPanel<DT, MC, NW, !TA> PA;       // A 'N' is contiguous along k
-    typedef DPanel<DT, NC, NW, TB> PB;        // B 'T' is contiguous along k
+    typedef DPanel<DT, MC, NW, !TA, DT::GES, KB> PA;   // A 'N' is contiguous along k
+    typedef DPanel<DT, NC, NW, TB, DT::GES, KB> PB;    // B 'T' is contiguous along k
+    static_assert(KC % DT::KF == 0, "a stage holds whole fragments");
     static constexpr int LOADS = PA::PER + PB::PER;
     static_assert(DT::LES == DT::GES && DT::PLANES == 1, "direct staging keeps the input format");
     static_assert(NS >= 2 && LDS_BYTES <= 160 * 1024, "LDS budget of one CU");
@@ -234,12 +313,12 @@ struct DTile {
         const char *pa = buf, *pb = buf + PANEL_A;
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
-            if constexpr (!TA) read_frag<DT>(pa, PANEL_A, wm * WTM + 16 * i, c, lane, fa[i]);
+            if constexpr (!TA) read_frag_k<DT, KB>(pa, wm * WTM + 16 * i, c, lane, fa[i]);
             else read_frag_tr<DT, MC>(pa, wm * WTM + 16 * i, c, lane, fa[i]);
         }
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-            if constexpr (TB) read_frag<DT>(pb, PANEL_B, wn * WTN + 16 * j, c, lane, fb[j]);
+            if constexpr (TB) read_frag_k<DT, KB>(pb, wn * WTN + 16 * j, c, lane, fb[j]);
             else read_frag_tr<DT, NC>(pb, wn * WTN + 16 * j, c, lane, fb[j]);
         }
     }

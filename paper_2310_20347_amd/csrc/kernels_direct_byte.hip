@@ -15,5 +15,9 @@ void register_direct_byte(std::vector<KernelCfg> &out)
 {
     add_byte_direct<TF8>(out, K_F8);
     add_byte_direct<TI8>(out, K_I8);
+    // INT8 fragments cover 64 bytes of k, so INT8 also has 64-byte stages: a
+    // deeper ring in the same LDS (FP8 fragments need all 128 bytes)
+    add_direct<TI8, 256, 256, 2, 4, 4, false, 64>(out, K_I8);
+    add_direct<TI8, 256, 256, 2, 4, 5, false, 64>(out, K_I8);
 }
 }  // namespace mg

@@ -10,6 +10,9 @@ static void add_half_direct(std::vector<KernelCfg> &out, int kclass)
     add_direct<DT, 256, 128, 2, 2, 3>(out, kclass);
     add_direct<DT, 128, 128, 2, 2, 4>(out, kclass);
     add_direct<DT, 128, 128, 2, 2, 2, true>(out, kclass);   // two workgroups per CU; also split-K
+    // 64-byte stages: a deeper ring (more loads in flight) in the same LDS
+    add_direct<DT, 256, 256, 2, 4, 4, false, 64>(out, kclass);
+    add_direct<DT, 256, 256, 2, 4, 5, false, 64>(out, kclass);
 }
 
 void register_direct_half(std::vector<KernelCfg> &out)

@@ -96,14 +96,14 @@ struct UTile {
             if constexpr (PKA) {
 #pragma unroll
                 for (int i = 0; i < FM; ++i) {
-                    if constexpr (!TA) read_frag<DT>(pa, PANEL_A, wm * WTM + 16 * i, c, lane, fa[i]);
+                    if constexpr (!TA) read_frag_k<DT, 128>(pa, wm * WTM + 16 * i, c, lane, fa[i]);
                     else read_frag_tr<DT, MC>(pa, wm * WTM + 16 * i, c, lane, fa[i]);
                 }
             }
             if constexpr (PKB) {
 #pragma unroll
                 for (int j = 0; j < FN; ++j) {
-                    if constexpr (TB) read_frag<DT>(pb, PANEL_B, wn * WTN + 16 * j, c, lane, fb[j]);
+                    if constexpr (TB) read_frag_k<DT, 128>(pb, wn * WTN + 16 * j, c, lane, fb[j]);
                     else read_frag_tr<DT, NC>(pb, wn * WTN + 16 * j, c, lane, fb[j]);
                 }
             }

@@ -33,8 +33,8 @@ struct SDTile {
     static __device__ __forceinline__ void read8(const char *panel, int r, int g, float v[8])
     {
         if constexpr (KMODE) {
-            const f32x4 x = *(const f32x4 *)(panel + lds_off<4>(r, 32 * g));
-            const f32x4 y = *(const f32x4 *)(panel + lds_off<4>(r, 32 * g + 16));
+            const f32x4 x = *(const f32x4 *)(panel + k_off<128>(r, 32 * g));
+            const f32x4 y = *(const f32x4 *)(panel + k_off<128>(r, 32 * g + 16));
             v[0] = x.x;
             v[1] = x.y;
             v[2] = x.z;
@@ -46,7 +46,7 @@ struct SDTile {
         } else {
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-                v[e] = *(const float *)(panel + mn_off<8>(8 * g + e, ROWS * 4, r * 4));
+                v[e] = *(const float *)(panel + mn_off<8, ROWS * 4, 8>(8 * g + e, r * 4));
         }
     }
 
