@@ -47,11 +47,11 @@ struct Shape {
     }
 };
 // A direct-staged 'N','N' tile shape (NS-deep LDS ring, 16-byte aligned operands).
-template <class DT, int MC, int NC, int NS>
+template <class DT, int MC, int NC, int NS, int KB = 128>
 struct DShape {
     typedef DT dt;
     static constexpr int mc = MC, nc = NC;
-    typedef DTile<DT, MC, NC, 2, 2, false, false, NS> NN;
+    typedef DTile<DT, MC, NC, 2, 2, false, false, NS, KB> NN;
     static constexpr int lds = NN::LDS_BYTES;
     static __device__ __forceinline__ void run(const GemmArgs &p, int tm, int tn, char *l)
     {

@@ -6,6 +6,10 @@
 // model of section 8.2): configurations whose kernels use scratch (spills;
 // section 8.7 shows a spilling micro-kernel losing half its speed) are
 // rejected, and so are configurations whose staged panels do not fit LDS.
+// A second phase re-times the few fastest candidates of each shape in
+// interleaved rounds: the MFMA-dense kernels run under a power limit whose
+// clock drifts by 10-15% between bursts, which decides close calls when each
+// candidate is timed in one burst.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -89,8 +93,14 @@ extern "C" int gemm_tune(int dtype, int64_t count, const int64_t *shapes, int re
         const int kclass = kclass_of(dtype, k);
         launch_fill(A, m * k, fill_kind(kclass), 1u, s);
         launch_fill(B, k * n, fill_kind(kclass), 2u, s);
-        double best_us = 1e300;
-        TuneVal best{0, 0, 8, 0.0};
+        struct Cand {
+            double us;
+            TuneVal v;
+            int reg, trans;
+            bool vec;
+            GemmArgs a;
+        };
+        std::vector<Cand> cands;
         const std::vector<int> &ids = g_by_class[kclass];
         for (size_t id = 0; id < ids.size(); ++id) {
             const KernelCfg &c = g_cfgs[ids[id]];
@@ -129,15 +139,50 @@ extern "C" int gemm_tune(int dtype, int64_t count, const int64_t *shapes, int re
                     if ((int)ms.size() != reps) continue;
                     std::sort(ms.begin(), ms.end());
                     const double us = 1e3 * ms[ms.size() / 2];
-                    if (us < best_us) {
-                        best_us = us;
-                        best = TuneVal{(int)id, order, kGroups[gi], us};
-                    }
+                    cands.push_back(Cand{us, TuneVal{(int)id, order, kGroups[gi], us}, reg, trans,
+                                         vec, a});
                     if (c.kind != 0) break;   // raster group is irrelevant to these
                 }
             }
         }
-        if (best_us < 1e300) {
+        if (cands.empty()) continue;
+        std::sort(cands.begin(), cands.end(),
+                  [](const Cand &x, const Cand &y) { return x.us < y.us; });
+        // phase two: the fastest candidates (those within 25% of the best),
+        // interleaved over rounds, median of all their launches
+        static constexpr int kFinal = 4, kRounds = 4;
+        size_t nf = 1;
+        while (nf < cands.size() && nf < (size_t)kFinal && cands[nf].us < 1.25 * cands[0].us) ++nf;
+        TuneVal best = cands[0].v;
+        if (nf > 1) {
+            std::vector<std::vector<float>> ms(nf);
+            for (int round = 0; round < kRounds; ++round) {
+                for (size_t q = 0; q < nf; ++q) {
+                    const Cand &c = cands[q];
+                    for (int r = 0; r < reps; ++r) {
+                        (void)hipEventRecord(e0, s);
+                        if (launch_gemm(g_cfgs[c.reg], c.trans, c.vec, c.a, s) != GEMM_OK) break;
+                        (void)hipEventRecord(e1, s);
+                        if ((e = hipEventSynchronize(e1)) != hipSuccess) return fail(e);
+                        float t = 0;
+                        (void)hipEventElapsedTime(&t, e0, e1);
+                        ms[q].push_back(t);
+                    }
+                }
+            }
+            double best_us = 1e300;
+            for (size_t q = 0; q < nf; ++q) {
+                if (ms[q].empty()) continue;
+                std::sort(ms[q].begin(), ms[q].end());
+                const double us = 1e3 * ms[q][ms[q].size() / 2];
+                if (us < best_us) {
+                    best_us = us;
+                    best = cands[q].v;
+                    best.us = us;
+                }
+            }
+        }
+        {
             std::lock_guard<std::mutex> g(g_mu);
             g_table[TuneKey{kclass, 0, bucket(m), bucket(n), bucket(k)}] = best;
         }
