@@ -88,6 +88,38 @@ int serve_layout(int64_t m, int64_t n, int64_t k, int dtype, int64_t *lda, int64
 int serve_run(const serve_config *cfg, int64_t count, const serve_request *reqs,
               serve_stats *stats, serve_outcome *outcomes);
 
+/*
+ * Queue mode: the same admission (FIFO, slots, arena budget, operand copies
+ * at admission) without steps.  One persistent kernel stays resident (one
+ * workgroup per compute unit by default, at most half of each compute
+ * unit's registers, so the operand copies still run beside it) and takes
+ * work from a ring of tile records in pinned host memory: a request is
+ * published tile by tile as soon as its operands have landed, and the
+ * kernel starts its tiles at once, between any two tiles of other requests.
+ * A request completes when its last tile is done; the kernel reports that
+ * through pinned host memory and the host polls it.  Tile shapes: 128x128
+ * (64x64 for the six-term split), the bodies of the grouped kernel's compact
+ * variant, so every result equals the standalone gemm() call bit for bit.
+ *
+ * Every wait in the kernel is bounded: after idle_polls empty polls of the
+ * ring (about 4 us each) the kernel leaves, and the host relaunches it when
+ * work is waiting (stats.launches counts the instances).  At the end the
+ * host sets a stop word and waits for the kernel to leave.  A request whose
+ * tiles do not fit the ring is rejected (GEMM_E_WORKSPACE).  stats.steps is
+ * 0; mean_requests_per_launch is completed requests per kernel instance.
+ */
+typedef struct {
+    int64_t ring_tiles;   /* tile records in the ring: a power of two in          */
+                          /* [1024, 2^24], or 0 for 65536 (128 bytes each)        */
+    int workgroups;       /* persistent workgroups, 0 = one per compute unit       */
+    int64_t idle_polls;   /* empty polls before the kernel leaves, 0 = 20000       */
+} serve_queue_config;
+
+/* Arguments: 1 cfg, 2 qcfg (NULL = defaults), 3 count, 4 reqs, 5 stats,
+ * 6 outcomes.  Returns as serve_run. */
+int serve_run_queue(const serve_config *cfg, const serve_queue_config *qcfg, int64_t count,
+                    const serve_request *reqs, serve_stats *stats, serve_outcome *outcomes);
+
 /* Simulated device for testing the scheduler without a GPU: a virtual clock,
  * a cost model per launch and forced failures. */
 typedef struct {

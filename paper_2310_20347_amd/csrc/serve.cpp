@@ -10,6 +10,10 @@
 // when its last launch has retired.  The scheduler talks to a Backend: the
 // real one (HIP) or a simulated one (virtual clock, cost model, forced
 // failures) used by the CPU tests.
+//
+// The queue mode (run_queue) has no steps: admitted requests are published
+// tile by tile to a persistent kernel that polls a host-written ring
+// (queue.hpp, queue.hip), and completions are read from host memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,6 +30,7 @@
 #include "abi_internal.hpp"
 #include "mgemm.h"
 #include "mgemm_serve.h"
+#include "queue.hpp"
 
 namespace mg {
 namespace {
@@ -55,6 +60,10 @@ struct Req {
     bool finished = false, failed = false, released = false, counted = false;
     double admit_t = -1, done_t = -1;
     int status = 0;
+    // queue mode
+    int qslot = -1, qgen = 0;
+    int64_t qtiles = 0;
+    double publish_t = -1;
 };
 
 struct Launch {
@@ -325,6 +334,65 @@ int check_requests(int64_t count, const serve_request *reqs, bool need_src)
     return 0;
 }
 
+// Outcomes and statistics of a finished run (both loops).
+void fill_stats(const serve_config &cfg, const std::vector<int64_t> &order, const std::vector<Req> &R,
+                int64_t peak_arena, int64_t peak_active, int64_t steps, int64_t launches,
+                int64_t reqs_in_launches, serve_stats *stats, serve_outcome *outcomes)
+{
+    std::vector<double> lat, lat_by[GEMM_NUM_DTYPES];
+    double t_first = kInf, t_last = 0, flops = 0;
+    int64_t completed = 0, failed = 0, rejected = 0;
+    for (size_t pos = 0; pos < order.size(); ++pos) {
+        const Req &r = R[(size_t)order[pos]];
+        if (r.finished) ++completed;
+        else if (r.status == GEMM_E_WORKSPACE) ++rejected;
+        else ++failed;
+        if (outcomes) {
+            serve_outcome &o = outcomes[r.idx];
+            o.admit_s = r.admit_t;
+            o.done_s = r.finished ? r.done_t : -1.0;
+            o.latency_ms = r.finished ? 1e3 * (r.done_t - r.in->arrival_s) : -1.0;
+            o.status = r.finished ? 0 : (r.status ? r.status : GEMM_E_SERVE);
+        }
+        if ((int64_t)pos < cfg.warmup_requests || !r.finished) continue;
+        const double ms = 1e3 * (r.done_t - r.in->arrival_s);
+        lat.push_back(ms);
+        lat_by[r.in->dtype].push_back(ms);
+        t_first = std::min(t_first, r.in->arrival_s);
+        t_last = std::max(t_last, r.done_t);
+        flops += 2.0 * r.in->m * r.in->n * r.in->k;
+    }
+    if (stats) {
+        std::memset(stats, 0, sizeof *stats);
+        stats->completed = completed;
+        stats->failed = failed;
+        stats->rejected = rejected;
+        stats->measured = (int64_t)lat.size();
+        stats->window_s = lat.empty() ? 0.0 : t_last - t_first;
+        stats->req_per_s = stats->window_s > 0 ? lat.size() / stats->window_s : 0.0;
+        stats->tflops = stats->window_s > 0 ? flops / stats->window_s / 1e12 : 0.0;
+        stats->p50_ms = percentile(lat, 0.50);
+        stats->p99_ms = percentile(lat, 0.99);
+        double sum = 0, mx = 0;
+        for (double v : lat) {
+            sum += v;
+            mx = std::max(mx, v);
+        }
+        stats->mean_ms = lat.empty() ? -1.0 : sum / lat.size();
+        stats->max_ms = lat.empty() ? -1.0 : mx;
+        for (int d = 0; d < GEMM_NUM_DTYPES; ++d) {
+            stats->count_by_dtype[d] = (int64_t)lat_by[d].size();
+            stats->p50_ms_by_dtype[d] = percentile(lat_by[d], 0.50);
+            stats->p99_ms_by_dtype[d] = percentile(lat_by[d], 0.99);
+        }
+        stats->steps = steps;
+        stats->launches = launches;
+        stats->peak_arena_bytes = peak_arena;
+        stats->peak_active = peak_active;
+        stats->mean_requests_per_launch = launches ? double(reqs_in_launches) / launches : 0.0;
+    }
+}
+
 int run(Backend &be, const serve_config &cfg, int64_t count, const serve_request *reqs,
         serve_stats *stats, serve_outcome *outcomes)
 {
@@ -518,60 +586,316 @@ int run(Backend &be, const serve_config &cfg, int64_t count, const serve_request
         }
     }
     be.end();
+    fill_stats(cfg, order, R, arena.peak(), peak_active, steps, launches, reqs_in_launches, stats,
+               outcomes);
+    return result;
+}
 
-    // statistics
-    std::vector<double> lat, lat_by[GEMM_NUM_DTYPES];
-    double t_first = kInf, t_last = 0, flops = 0;
-    int64_t completed = 0, failed = 0, rejected = 0;
-    for (size_t pos = 0; pos < order.size(); ++pos) {
-        const Req &r = R[(size_t)order[pos]];
-        if (r.finished) ++completed;
-        else if (r.status == GEMM_E_WORKSPACE) ++rejected;
-        else ++failed;
-        if (outcomes) {
-            serve_outcome &o = outcomes[r.idx];
-            o.admit_s = r.admit_t;
-            o.done_s = r.finished ? r.done_t : -1.0;
-            o.latency_ms = r.finished ? 1e3 * (r.done_t - r.in->arrival_s) : -1.0;
-            o.status = r.finished ? 0 : (r.status ? r.status : GEMM_E_SERVE);
-        }
-        if ((int64_t)pos < cfg.warmup_requests || !r.finished) continue;
-        const double ms = 1e3 * (r.done_t - r.in->arrival_s);
-        lat.push_back(ms);
-        lat_by[r.in->dtype].push_back(ms);
-        t_first = std::min(t_first, r.in->arrival_s);
-        t_last = std::max(t_last, r.done_t);
-        flops += 2.0 * r.in->m * r.in->n * r.in->k;
+
+// ---------------------------------------------------------------------------
+// Queue mode: one persistent kernel fed through a host-written ring.
+// ---------------------------------------------------------------------------
+constexpr int64_t kRingDefault = 1 << 16;
+constexpr int64_t kIdleDefault = 20000;
+
+// Tile shape of a request's dtype class in the queue kernel.
+int64_t queue_tiles(const serve_request &q, int64_t *mc_out = nullptr, int64_t *nc_out = nullptr)
+{
+    const int64_t t = kclass_of(q.dtype, q.k) == K_SPLIT3 ? 64 : 128;
+    if (mc_out) *mc_out = t;
+    if (nc_out) *nc_out = t;
+    return ((q.m + t - 1) / t) * ((q.n + t - 1) / t);
+}
+
+// Device and pinned resources of one queue run.
+struct QueueRes {
+    char *base = nullptr;             // the arena
+    QTile *ring_h = nullptr, *ring_d = nullptr;
+    QCtl *ctl_h = nullptr, *ctl_d = nullptr;
+    int *done_h = nullptr, *done_d = nullptr;
+    QDev *dev = nullptr;
+    size_t dev_bytes = 0;
+    hipStream_t ks = nullptr, cs = nullptr;   // kernel, copies
+    hipEvent_t kev = nullptr;                 // kernel instance finished
+    std::vector<hipEvent_t> cev;              // per slot: operand copies finished
+
+    int init(const serve_config &cfg, int64_t ring)
+    {
+        hipError_t e;
+        const int slots = cfg.max_active;
+        if ((e = hipMalloc((void **)&base, (size_t)std::max<int64_t>(cfg.budget_bytes, kAlign))) != hipSuccess)
+            return fail(e);
+        const unsigned fl = hipHostMallocMapped | hipHostMallocCoherent;
+        if ((e = hipHostMalloc((void **)&ring_h, (size_t)ring * sizeof(QTile), fl)) != hipSuccess) return fail(e);
+        if ((e = hipHostMalloc((void **)&ctl_h, sizeof(QCtl), fl)) != hipSuccess) return fail(e);
+        if ((e = hipHostMalloc((void **)&done_h, (size_t)slots * sizeof(int), fl)) != hipSuccess) return fail(e);
+        std::memset(ring_h, 0, (size_t)ring * sizeof(QTile));
+        std::memset(ctl_h, 0, sizeof(QCtl));
+        std::memset(done_h, 0, (size_t)slots * sizeof(int));
+        if ((e = hipHostGetDevicePointer((void **)&ring_d, ring_h, 0)) != hipSuccess) return fail(e);
+        if ((e = hipHostGetDevicePointer((void **)&ctl_d, ctl_h, 0)) != hipSuccess) return fail(e);
+        if ((e = hipHostGetDevicePointer((void **)&done_d, done_h, 0)) != hipSuccess) return fail(e);
+        dev_bytes = offsetof(QDev, counters) + (size_t)slots * sizeof(int32_t);
+        if ((e = hipMalloc((void **)&dev, dev_bytes)) != hipSuccess) return fail(e);
+        if ((e = hipStreamCreateWithFlags(&ks, hipStreamNonBlocking)) != hipSuccess) return fail(e);
+        if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return fail(e);
+        if ((e = hipEventCreateWithFlags(&kev, hipEventDisableTiming)) != hipSuccess) return fail(e);
+        cev.assign((size_t)slots, nullptr);
+        for (auto &ev : cev)
+            if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return fail(e);
+        if ((e = hipMemsetAsync(dev, 0, dev_bytes, ks)) != hipSuccess) return fail(e);
+        if ((e = hipStreamSynchronize(ks)) != hipSuccess) return fail(e);
+        return GEMM_OK;
     }
-    if (stats) {
-        std::memset(stats, 0, sizeof *stats);
-        stats->completed = completed;
-        stats->failed = failed;
-        stats->rejected = rejected;
-        stats->measured = (int64_t)lat.size();
-        stats->window_s = lat.empty() ? 0.0 : t_last - t_first;
-        stats->req_per_s = stats->window_s > 0 ? lat.size() / stats->window_s : 0.0;
-        stats->tflops = stats->window_s > 0 ? flops / stats->window_s / 1e12 : 0.0;
-        stats->p50_ms = percentile(lat, 0.50);
-        stats->p99_ms = percentile(lat, 0.99);
-        double sum = 0, mx = 0;
-        for (double v : lat) {
-            sum += v;
-            mx = std::max(mx, v);
-        }
-        stats->mean_ms = lat.empty() ? -1.0 : sum / lat.size();
-        stats->max_ms = lat.empty() ? -1.0 : mx;
-        for (int d = 0; d < GEMM_NUM_DTYPES; ++d) {
-            stats->count_by_dtype[d] = (int64_t)lat_by[d].size();
-            stats->p50_ms_by_dtype[d] = percentile(lat_by[d], 0.50);
-            stats->p99_ms_by_dtype[d] = percentile(lat_by[d], 0.99);
-        }
-        stats->steps = steps;
-        stats->launches = launches;
-        stats->peak_arena_bytes = arena.peak();
-        stats->peak_active = peak_active;
-        stats->mean_requests_per_launch = launches ? double(reqs_in_launches) / launches : 0.0;
+    // Frees everything; the kernel must have left (the caller synchronises).
+    void free_all()
+    {
+        for (auto &ev : cev)
+            if (ev) (void)hipEventDestroy(ev);
+        cev.clear();
+        if (kev) (void)hipEventDestroy(kev);
+        if (cs) (void)hipStreamDestroy(cs);
+        if (ks) (void)hipStreamDestroy(ks);
+        if (dev) (void)hipFree(dev);
+        if (done_h) (void)hipHostFree(done_h);
+        if (ctl_h) (void)hipHostFree(ctl_h);
+        if (ring_h) (void)hipHostFree(ring_h);
+        if (base) (void)hipFree(base);
+        *this = QueueRes();
     }
+    static int fail(hipError_t e)
+    {
+        t_tls.hip_err = (int)e;
+        return GEMM_E_HIP;
+    }
+};
+
+int run_queue(const serve_config &cfg, const serve_queue_config &qc, int64_t count,
+              const serve_request *reqs, int cus, serve_stats *stats, serve_outcome *outcomes)
+{
+    std::vector<Req> R((size_t)count);
+    for (int64_t i = 0; i < count; ++i) {
+        Req &r = R[(size_t)i];
+        r.idx = i;
+        r.in = &reqs[i];
+        serve_layout(r.in->m, r.in->n, r.in->k, r.in->dtype, &r.lda, &r.ldb, &r.ldc, &r.bytes);
+        r.a_bytes = round_up(r.in->m * r.lda * in_bytes(r.in->dtype), kAlign);
+        r.b_bytes = round_up(r.in->k * r.ldb * in_bytes(r.in->dtype), kAlign);
+        r.qtiles = queue_tiles(*r.in);
+    }
+    std::vector<int64_t> order((size_t)count);
+    for (int64_t i = 0; i < count; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
+
+    const int64_t ring = qc.ring_tiles > 0 ? qc.ring_tiles : kRingDefault;
+    const int64_t idle = qc.idle_polls > 0 ? qc.idle_polls : kIdleDefault;
+    const int grid = qc.workgroups > 0 ? qc.workgroups : cus;
+    QueueRes q;
+    int rc = q.init(cfg, ring);
+    if (rc != GEMM_OK) {
+        (void)hipDeviceSynchronize();
+        q.free_all();
+        return rc;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    auto now_s = [&]() {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    };
+    int64_t launches = 0;
+    bool running = false;
+    auto launch = [&]() {
+        int r2 = launch_queue_kernel(q.ring_d, ring - 1, q.ctl_d, q.done_d, q.dev, idle, grid, q.ks);
+        if (r2 == GEMM_OK && hipEventRecord(q.kev, q.ks) != hipSuccess) r2 = GEMM_E_HIP;
+        if (r2 == GEMM_OK) {
+            ++launches;
+            running = true;
+        }
+        return r2;
+    };
+    int result = launch();
+
+    Arena arena;
+    arena.init(cfg.budget_bytes);
+    std::deque<int64_t> queue, copying;
+    std::vector<int64_t> published;
+    std::vector<int> free_slots, slot_gen((size_t)cfg.max_active, 0);
+    for (int i = cfg.max_active - 1; i >= 0; --i) free_slots.push_back(i);
+    size_t next_arrival = 0;
+    int64_t done = 0, peak_active = 0, active = 0, tail = 0, completed_tiles = 0;
+
+    auto finish = [&](Req &r) {
+        ++done;
+        if (r.off >= 0) {
+            arena.release(r.off, r.bytes);
+            r.off = -1;
+        }
+        if (r.qslot >= 0) {
+            free_slots.push_back(r.qslot);
+            r.qslot = -1;
+            --active;
+        }
+    };
+
+    while (result == GEMM_OK && done < count) {
+        const double now = now_s();
+        bool progressed = false;
+        while (next_arrival < order.size() && reqs[order[next_arrival]].arrival_s <= now)
+            queue.push_back(order[next_arrival++]);
+        // admission: FIFO; the operands are copied into the arena on the copy stream
+        while (!queue.empty() && !free_slots.empty()) {
+            Req &r = R[(size_t)queue.front()];
+            if (round_up(r.bytes, kAlign) > cfg.budget_bytes || r.qtiles > ring) {
+                r.status = GEMM_E_WORKSPACE;
+                queue.pop_front();
+                finish(r);
+                continue;
+            }
+            const int64_t off = arena.alloc(r.bytes);
+            if (off < 0) break;
+            queue.pop_front();
+            r.off = off;
+            r.admit_t = now;
+            r.qslot = free_slots.back();
+            free_slots.pop_back();
+            peak_active = std::max(peak_active, ++active);
+            const int es = in_bytes(r.in->dtype);
+            hipError_t e = hipMemcpyAsync(q.base + r.off, r.in->a_src, (size_t)(r.in->m * r.lda * es),
+                                          hipMemcpyDeviceToDevice, q.cs);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(q.base + r.off + r.a_bytes, r.in->b_src,
+                                   (size_t)(r.in->k * r.ldb * es), hipMemcpyDeviceToDevice, q.cs);
+            if (e == hipSuccess) e = hipEventRecord(q.cev[(size_t)r.qslot], q.cs);
+            if (e != hipSuccess) {
+                t_tls.hip_err = (int)e;
+                r.failed = true;
+                r.status = GEMM_E_SERVE;
+                finish(r);
+                continue;
+            }
+            copying.push_back(r.idx);
+            progressed = true;
+        }
+        // publication: requests whose operands have landed, while the ring has room
+        while (!copying.empty()) {
+            Req &r = R[(size_t)copying.front()];
+            const hipError_t e = hipEventQuery(q.cev[(size_t)r.qslot]);
+            if (e == hipErrorNotReady) break;
+            if (e != hipSuccess) {
+                t_tls.hip_err = (int)e;
+                result = GEMM_E_SERVE;
+                break;
+            }
+            if (tail + r.qtiles - completed_tiles > ring) break;
+            int64_t mc = 128, nc = 128;
+            queue_tiles(*r.in, &mc, &nc);
+            const int kclass = kclass_of(r.in->dtype, r.in->k);
+            GemmArgs a;
+            std::memset(&a, 0, sizeof a);
+            a.A = q.base + r.off;
+            a.B = q.base + r.off + r.a_bytes;
+            a.C = q.base + r.off + r.a_bytes + r.b_bytes;
+            a.lda = r.lda;
+            a.ldb = r.ldb;
+            a.ldc = r.ldc;
+            a.m = (int)r.in->m;
+            a.n = (int)r.in->n;
+            a.k = (int)r.in->k;
+            a.alpha = 1.0f;
+            a.beta = 0.0f;
+            a.ialpha = 1;
+            a.ibeta = 0;
+            a.tiles_m = (int)((r.in->m + mc - 1) / mc);
+            a.tiles_n = (int)((r.in->n + nc - 1) / nc);
+            a.order = 0;
+            a.group = 8;
+            a.terms = split_terms(kclass);
+            r.qgen = ++slot_gen[(size_t)r.qslot];
+            for (int64_t t = 0; t < r.qtiles; ++t) {
+                QTile &rec = q.ring_h[(tail + t) & (ring - 1)];
+                rec.a = a;
+                rec.t = (int)t;
+                rec.slot = r.qslot;
+                rec.ntiles = (int)r.qtiles;
+                rec.body = kclass;
+                rec.gen = r.qgen;
+            }
+            tail += r.qtiles;
+            __atomic_store_n(&q.ctl_h->tail, tail, __ATOMIC_RELEASE);
+            r.publish_t = now_s();
+            published.push_back(r.idx);
+            copying.pop_front();
+            progressed = true;
+        }
+        if (result != GEMM_OK) break;
+        // completions, in any order
+        for (size_t i = 0; i < published.size();) {
+            Req &r = R[(size_t)published[i]];
+            if (__atomic_load_n(&q.done_h[r.qslot], __ATOMIC_ACQUIRE) == r.qgen) {
+                r.finished = true;
+                r.done_t = now_s();
+                if (r.in->result) {
+                    const char *c = q.base + r.off + r.a_bytes + r.b_bytes;
+                    if (hipMemcpyAsync(r.in->result, c, (size_t)(r.in->m * r.ldc * 4), hipMemcpyDeviceToHost,
+                                       q.cs) != hipSuccess ||
+                        hipStreamSynchronize(q.cs) != hipSuccess) {
+                        r.finished = false;
+                        r.failed = true;
+                        r.status = GEMM_E_SERVE;
+                    }
+                }
+                completed_tiles += r.qtiles;
+                finish(r);
+                published[i] = published.back();
+                published.pop_back();
+                progressed = true;
+                continue;
+            }
+            if (now - r.publish_t > cfg.watchdog_s) {
+                result = GEMM_E_SERVE;
+                break;
+            }
+            ++i;
+        }
+        if (result != GEMM_OK) break;
+        // a kernel instance that left while idle is relaunched when work is waiting
+        if (running && hipEventQuery(q.kev) == hipSuccess) running = false;
+        if (!running && !published.empty()) {
+            QDev h;
+            std::memset(&h, 0, sizeof h);
+            hipError_t e = hipMemcpyAsync(&h.tail, &q.dev->tail, sizeof h.tail, hipMemcpyDeviceToHost, q.ks);
+            if (e == hipSuccess) e = hipStreamSynchronize(q.ks);
+            h.claim = h.tail;
+            h.stop = 0;
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(q.dev, &h, offsetof(QDev, counters), hipMemcpyHostToDevice, q.ks);
+            if (e == hipSuccess) e = hipStreamSynchronize(q.ks);
+            if (e != hipSuccess) {
+                t_tls.hip_err = (int)e;
+                result = GEMM_E_SERVE;
+                break;
+            }
+            result = launch();
+            progressed = true;
+        }
+        if (!progressed) {
+            // completions are polled, so never sleep long
+            double dt = 20e-6;
+            if (next_arrival < order.size()) dt = std::min(dt, reqs[order[next_arrival]].arrival_s - now);
+            if (dt > 2e-6) std::this_thread::sleep_for(std::chrono::duration<double>(dt));
+            else std::this_thread::yield();
+        }
+    }
+    // the kernel leaves on the stop word (or, at the latest, after its idle bound)
+    __atomic_store_n(&q.ctl_h->stop, 1, __ATOMIC_RELEASE);
+    (void)hipStreamSynchronize(q.ks);
+    (void)hipStreamSynchronize(q.cs);
+    q.free_all();
+    for (int64_t i = 0; i < count; ++i) {
+        Req &r = R[(size_t)i];
+        if (!r.finished && !r.failed && r.status == 0) r.status = GEMM_E_SERVE;
+    }
+    fill_stats(cfg, order, R, arena.peak(), peak_active, 0, launches, done, stats, outcomes);
     return result;
 }
 
@@ -615,6 +939,26 @@ int serve_run(const serve_config *cfg, int64_t count, const serve_request *reqs,
     if (rc != GEMM_OK) return rc;
     HipBackend be;
     return run(be, *cfg, count, reqs, stats, outcomes);
+}
+
+int serve_run_queue(const serve_config *cfg, const serve_queue_config *qcfg, int64_t count,
+                    const serve_request *reqs, serve_stats *stats, serve_outcome *outcomes)
+{
+    if (check_config(cfg)) return -1;
+    serve_queue_config qc;
+    std::memset(&qc, 0, sizeof qc);
+    if (qcfg) qc = *qcfg;
+    if (qc.ring_tiles < 0 || (qc.ring_tiles > 0 && (qc.ring_tiles < 1024 || qc.ring_tiles > (1 << 24) ||
+                                                    (qc.ring_tiles & (qc.ring_tiles - 1)))) ||
+        qc.workgroups < 0 || qc.workgroups > 8192 || qc.idle_polls < 0)
+        return -2;
+    int v = check_requests(count, reqs, true);
+    if (v) return v - 1;
+    ensure_registered();
+    DevState *d = nullptr;
+    int rc = device_state(&d);
+    if (rc != GEMM_OK) return rc;
+    return run_queue(*cfg, qc, count, reqs, d->cus, stats, outcomes);
 }
 
 int serve_run_sim(const serve_config *cfg, int64_t count, const serve_request *reqs,

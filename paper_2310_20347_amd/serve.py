@@ -45,6 +45,10 @@ class Outcome(ctypes.Structure):
     _fields_ = [("admit_s", _D), ("done_s", _D), ("latency_ms", _D), ("status", _INT)]
 
 
+class QueueConfig(ctypes.Structure):
+    _fields_ = [("ring_tiles", _I64), ("workgroups", _INT), ("idle_polls", _I64)]
+
+
 class Sim(ctypes.Structure):
     _fields_ = [("launch_overhead_s", _D), ("flops_per_s", _D), ("bytes_per_s", _D),
                 ("fail_launch", _I64), ("hang_launch", _I64)]
@@ -68,6 +72,10 @@ def _setup():
                                     ctypes.POINTER(Sim), ctypes.POINTER(Stats),
                                     ctypes.POINTER(Outcome)]
         L.serve_run_sim.restype = _INT
+        L.serve_run_queue.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(QueueConfig), _I64,
+                                      ctypes.POINTER(Request), ctypes.POINTER(Stats),
+                                      ctypes.POINTER(Outcome)]
+        L.serve_run_queue.restype = _INT
         _ready = True
     return L
 
@@ -113,4 +121,22 @@ def serve_run_sim(cfg: Config, reqs: Sequence[Any], sim: Sim, check: bool = Fals
                                 ctypes.byref(st), oc)
     if check:
         _check(rc, "serve_run_sim")
+    return rc, st, list(oc)[:len(reqs)]
+
+
+def queue_config(ring_tiles=0, workgroups=0, idle_polls=0) -> QueueConfig:
+    return QueueConfig(ring_tiles, workgroups, idle_polls)
+
+
+def serve_run_queue(cfg: Config, reqs: Sequence[Any], qcfg: Optional[QueueConfig] = None,
+                    check: bool = True):
+    """Queue mode on the GPU (persistent kernel fed through a host ring);
+    returns (rc, Stats, list of Outcome)."""
+    arr = _requests(reqs)
+    st = Stats()
+    oc = (Outcome * max(1, len(reqs)))()
+    q = ctypes.byref(qcfg) if qcfg is not None else None
+    rc = _setup().serve_run_queue(ctypes.byref(cfg), q, len(reqs), arr, ctypes.byref(st), oc)
+    if check:
+        _check(rc, "serve_run_queue")
     return rc, st, list(oc)[:len(reqs)]

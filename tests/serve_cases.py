@@ -53,3 +53,67 @@ def workload(count, rate, seed, pools, lo=16, hi=4096, result_every=0):
         meta.append(dict(m=m, n=n, k=k, dtype=dt, lda=lda, ldb=ldb, ldc=ldc, a_off=a_off,
                          b_off=b_off, result=res))
     return reqs, meta
+
+
+def alone(pools, md):
+    """The request run by itself through gemm() with an unsliced configuration
+    (not split-K): the serving launches run unsliced tiles, and every unsliced
+    configuration sums k in one order."""
+    import torch
+    m, n, k, dt = md["m"], md["n"], md["k"], md["dtype"]
+    out_t = torch.int32 if dt == mg.GEMM_I8 else torch.float32
+    C = torch.zeros((m, n), dtype=out_t, device="cuda")
+    mg.force_config(dt, 1, 0)
+    try:
+        mg.gemm("N", "N", m, n, k, 1, pools.ptr(dt, md["a_off"]), md["lda"],
+                pools.ptr(dt, md["b_off"]), md["ldb"], 0, C, n, dt)
+    finally:
+        mg.force_config(dt, -1, 0)
+    torch.cuda.synchronize()
+    return C.cpu().numpy()
+
+
+def host_operand(pools, dt, off, rows, ld):
+    t = pools.t[dt]
+    es = t.element_size()
+    flat = t.cpu().numpy().reshape(-1)
+    x = flat[off // es: off // es + rows * ld].reshape(rows, ld)
+    if dt == mg.GEMM_BF16:
+        x = x.view(np.uint16)
+    return x
+
+
+def check_results(pools, meta):
+    """Every request that returned its C: equal to the request alone (bit for
+    bit) and within the quantised-input tolerance of the oracle.  Returns the
+    number checked."""
+    import oracle
+    from gemm_cases import QUANT_TOL, decode, terms_for
+    checked = 0
+    for md in meta:
+        if md["result"] is None:
+            continue
+        mix = md["result"]
+        solo = alone(pools, md)
+        assert np.array_equal(mix, solo), f"mix != alone for {md['m']}x{md['n']}x{md['k']}"
+        dt, m, n, k = md["dtype"], md["m"], md["n"], md["k"]
+        A = host_operand(pools, dt, md["a_off"], m, md["lda"])
+        B = host_operand(pools, dt, md["b_off"], k, md["ldb"])
+        if dt == mg.GEMM_I8:
+            ref = oracle.gemm_i8("N", "N", m, n, k, 1, A, md["lda"], B, md["ldb"])
+            assert np.array_equal(mix, ref)
+        else:
+            terms = terms_for(dt, k)
+            if terms is not None:
+                npc = 3 if len(terms) > 3 else 2
+                PA = [oracle.decode_bf16(x) for x in oracle.split_bf16(A, npc)]
+                PB = [oracle.decode_bf16(x) for x in oracle.split_bf16(B, npc)]
+                ref = oracle.gemm_pieces("N", "N", m, n, k, 1.0, PA, md["lda"], PB, md["ldb"], terms)
+                ma, mb = np.abs(A).max(), np.abs(B).max()
+            else:
+                Aq, Bq = decode(A, dt), decode(B, dt)
+                ref = oracle.gemm_f64("N", "N", m, n, k, 1.0, Aq, md["lda"], Bq, md["ldb"])
+                ma, mb = np.abs(Aq).max(), np.abs(Bq).max()
+            assert oracle.normalized_error(mix, ref, k, ma, mb) <= QUANT_TOL
+        checked += 1
+    return checked

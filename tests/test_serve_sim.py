@@ -120,3 +120,14 @@ def test_invalid_configuration_and_requests():
     assert sv.serve_run_sim(sv.config(), r, sim())[0] == -3
     assert sv.serve_run_sim(sv.config(), reqs_of([(8, 8, 8)], [0.0], [1]),
                             sv.Sim(0, 0, 1, -1, -1))[0] == -4
+
+
+def test_queue_mode_rejects_invalid_arguments_before_touching_the_device():
+    r = reqs_of([(8, 8, 8)], [0.0], [mg.GEMM_BF16])
+    assert sv.serve_run_queue(sv.config(max_active=0), r, check=False)[0] == -1
+    assert sv.serve_run_queue(sv.config(), r, sv.queue_config(ring_tiles=1000), check=False)[0] == -2
+    assert sv.serve_run_queue(sv.config(), r, sv.queue_config(ring_tiles=512), check=False)[0] == -2
+    assert sv.serve_run_queue(sv.config(), r, sv.queue_config(idle_polls=-1), check=False)[0] == -2
+    assert sv.serve_run_queue(sv.config(), r, sv.queue_config(workgroups=-3), check=False)[0] == -2
+    r[0].m = 0
+    assert sv.serve_run_queue(sv.config(), r, check=False)[0] == -4
