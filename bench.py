@@ -382,7 +382,9 @@ def grouped_bench(mg, torch, stream, reps=10):
 
 def serving_bench(mg, torch, rates=(2000, 5000, 10000, 20000), count=3000, warmup=300):
     """The serving workload: Poisson arrivals, shapes as the batching workload,
-    dtype mix 50% split-product FP32 / 30% BF16 / 20% INT8, 64 GiB budget."""
+    dtype mix 50% split-product FP32 / 30% BF16 / 20% INT8, 64 GiB budget;
+    run by the step loop (grouped launches) and by the queue mode (one
+    persistent kernel fed through a host ring), same requests."""
     from paper_2310_20347_amd import inputs
     from paper_2310_20347_amd import serve as sv
     pool_bytes = 128 << 20
@@ -405,17 +407,23 @@ def serving_bench(mg, torch, rates=(2000, 5000, 10000, 20000), count=3000, warmu
                                    pools[dt].data_ptr(), None))
         cfg = sv.config(budget_bytes=64 << 30, max_active=512, warmup_requests=warmup)
         rc, st, _ = sv.serve_run(cfg, reqs)
-        out[str(rate)] = {
-            "offered_req_per_s": rate, "req_per_s": round(st.req_per_s, 1),
-            "tflops": round(st.tflops, 3), "p50_ms": round(st.p50_ms, 4),
-            "p99_ms": round(st.p99_ms, 4), "max_ms": round(st.max_ms, 3),
-            "completed": st.completed, "failed": st.failed, "rejected": st.rejected,
-            "req_per_launch": round(st.mean_requests_per_launch, 2),
-            "peak_arena_gb": round(st.peak_arena_bytes / 1e9, 3),
+        out[str(rate)] = _serve_summary(st, names, mix)
+        out[str(rate)]["offered_req_per_s"] = rate
+        out[str(rate)]["req_per_launch"] = round(st.mean_requests_per_launch, 2)
+        rc, st, _ = sv.serve_run_queue(cfg, reqs)
+        out[str(rate)]["queue_mode"] = _serve_summary(st, names, mix)
+        out[str(rate)]["queue_mode"]["kernel_launches"] = st.launches
+    return out
+
+
+def _serve_summary(st, names, mix):
+    return {"req_per_s": round(st.req_per_s, 1), "tflops": round(st.tflops, 3),
+            "p50_ms": round(st.p50_ms, 4), "p99_ms": round(st.p99_ms, 4),
+            "max_ms": round(st.max_ms, 3), "completed": st.completed, "failed": st.failed,
+            "rejected": st.rejected, "peak_arena_gb": round(st.peak_arena_bytes / 1e9, 3),
             "by_dtype": {names[d]: {"count": st.count_by_dtype[d],
                                     "p50_ms": round(st.p50_ms_by_dtype[d], 4),
                                     "p99_ms": round(st.p99_ms_by_dtype[d], 4)} for d in mix}}
-    return out
 
 
 if __name__ == "__main__":

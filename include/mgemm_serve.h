@@ -89,17 +89,17 @@ int serve_run(const serve_config *cfg, int64_t count, const serve_request *reqs,
               serve_stats *stats, serve_outcome *outcomes);
 
 /*
- * Queue mode: the same admission (FIFO, slots, arena budget, operand copies
- * at admission) without steps.  One persistent kernel stays resident (one
- * workgroup per compute unit by default, at most half of each compute
- * unit's registers, so the operand copies still run beside it) and takes
- * work from a ring of tile records in pinned host memory: a request is
- * published tile by tile as soon as its operands have landed, and the
- * kernel starts its tiles at once, between any two tiles of other requests.
- * A request completes when its last tile is done; the kernel reports that
- * through pinned host memory and the host polls it.  Tile shapes: 128x128
- * (64x64 for the six-term split), the bodies of the grouped kernel's compact
- * variant, so every result equals the standalone gemm() call bit for bit.
+ * Queue mode: the same admission (FIFO, slots, arena budget) without steps.
+ * One persistent kernel stays resident (one workgroup per compute unit,
+ * at most half of each unit's registers) and takes work from a ring of tile
+ * records in pinned host memory.  A request is published at admission as
+ * copy tiles (its A and B into the arena, 256 KiB each, done by the kernel)
+ * followed by its output tiles, which wait for those copies; the kernel
+ * runs them between any two tiles of other requests.  A request completes
+ * when its last output tile is done; the kernel reports that through pinned
+ * host memory and the host polls it.  Output tiles: 128x128 (64x64 for the
+ * six-term split), the bodies of the grouped kernel's compact variant, so
+ * every result equals the standalone gemm() call bit for bit.
  *
  * Every wait in the kernel is bounded: after idle_polls empty polls of the
  * ring (about 4 us each) the kernel leaves, and the host relaunches it when
@@ -111,7 +111,8 @@ int serve_run(const serve_config *cfg, int64_t count, const serve_request *reqs,
 typedef struct {
     int64_t ring_tiles;   /* tile records in the ring: a power of two in          */
                           /* [1024, 2^24], or 0 for 65536 (128 bytes each)        */
-    int workgroups;       /* persistent workgroups, 0 = one per compute unit       */
+    int workgroups;       /* persistent workgroups, 0 = one per compute unit;      */
+                          /* larger values are reduced to that                     */
     int64_t idle_polls;   /* empty polls before the kernel leaves, 0 = 20000       */
 } serve_queue_config;
 

@@ -1,7 +1,8 @@
 // Device-side request queue: the records shared by the host loop
 // (serve_run_queue in serve.cpp) and the persistent kernel (queue.hip).
 //
-// The host publishes work as output tiles.  Tile records live in a ring in
+// The host publishes work as tiles: a request's copy tiles (its operands
+// into the arena), then its output tiles.  Tile records live in a ring in
 // pinned, fine-grained host memory; `tail` (also host memory) counts the
 // tiles published so far.  Workgroups of the persistent kernel claim tile
 // indices in order from a device counter; the one workgroup whose claim
@@ -9,7 +10,8 @@
 // and copies it to device memory, so only one workgroup reads across PCIe
 // while the queue is empty.  When the last tile of a request is done, its
 // workgroup writes the request's generation number to `done[slot]` in host
-// memory.
+// memory.  An output tile waits (bounded) for its request's copy tiles,
+// which were published, and so claimed, before it.
 #pragma once
 
 #include <stdint.h>
@@ -18,41 +20,50 @@
 
 namespace mg {
 
-// One published output tile: the request's arguments and the tile's index
-// in its raster (128 bytes, copied into LDS by 8 lanes).
+// One published unit of work (128 bytes, copied into LDS by 8 lanes):
+//   kind 1, a copy tile: a.lda bytes from a.A to a.C (a request's operands
+//     materialised in the arena at admission, in chunks of kCopyChunk);
+//   kind 0, an output tile: the request's arguments and the tile's index in
+//     its raster; it starts once the request's ncopy copy tiles are done.
 struct QTile {
-    GemmArgs a;      // the request (row-major 'N','N', alpha 1, beta 0)
+    GemmArgs a;      // the request (row-major 'N','N', alpha 1, beta 0), or the copy
     int t;           // tile index within the request, 0 .. ntiles-1
-    int slot;        // request slot: index into done[] and the tile counters
-    int ntiles;      // tiles of the request
+    int slot;        // request slot: index into done[] and the device counters
+    int ntiles;      // output tiles of the request
     int body;        // tile body: the request's dtype class (KClass)
     int gen;         // value written to done[slot] when the request completes
-    int pad[3];
+    int kind;        // 0 output tile, 1 copy tile
+    int ncopy;       // copy tiles of the request
+    int pad;
 };
+constexpr int64_t kCopyChunk = 256 << 10;   // bytes per copy tile
 static_assert(sizeof(QTile) == 128, "tile records are 128 bytes");
 
-// Host-written control words (pinned host memory).
+// Control words in pinned host memory: tail and stop written by the host,
+// fault by the kernel.
 struct QCtl {
     int64_t tail;    // tiles published
     int32_t stop;    // set by the host when no more work will come
-    int32_t pad[13];
+    int32_t fault;   // set by the kernel: an output tile's operands never arrived
+    int32_t pad[12];
 };
 
 // Device-memory state of the queue.  claim and tail are reset by the host
-// between kernel instances; counters reset themselves (the last tile of a
-// request sets its slot's counter back to zero).
+// between kernel instances; the per-slot counters reset themselves (the last
+// output tile of a request sets both of its slot's counters back to zero).
 struct QDev {
     int64_t claim;   // next tile index to hand out
     int64_t tail;    // the device's copy of the published tail
     int32_t stop;    // set by the frontier: every workgroup leaves
     int32_t pad[11];
-    int32_t counters[1];   // [slots]: finished tiles of the slot's request
+    int32_t counters[1];   // [2 * slots]: finished output tiles of the slot's request,
+                           // then finished copy tiles
 };
 
 // Launches the persistent kernel: `grid` workgroups of 256 threads.
 // idle_polls bounds the frontier's consecutive empty polls of the host tail
 // before the whole kernel leaves (the host relaunches it when work comes).
-int launch_queue_kernel(const QTile *ring, int64_t ring_mask, const QCtl *ctl, int *done,
-                        QDev *dev, int64_t idle_polls, int grid, hipStream_t s);
+int launch_queue_kernel(const QTile *ring, int64_t ring_mask, QCtl *ctl, int *done, QDev *dev,
+                        int slots, int64_t idle_polls, int grid, hipStream_t s);
 
 }  // namespace mg

@@ -62,7 +62,7 @@ struct Req {
     int status = 0;
     // queue mode
     int qslot = -1, qgen = 0;
-    int64_t qtiles = 0;
+    int64_t qtiles = 0, qcopies = 0;
     double publish_t = -1;
 };
 
@@ -122,6 +122,16 @@ private:
     int64_t used_ = 0, peak_ = 0;
 };
 
+// The host loops poll (events, completion words), so they yield rather than
+// sleep: a sleep of a few microseconds lasts tens (the kernel's timer
+// slack).  They sleep only when nothing is outstanding and the next arrival
+// is far off.
+void idle_wait(double dt, bool outstanding)
+{
+    if (!outstanding && dt > 300e-6) std::this_thread::sleep_for(std::chrono::duration<double>(dt - 200e-6));
+    else std::this_thread::yield();
+}
+
 class Backend {
 public:
     virtual ~Backend() {}
@@ -179,13 +189,7 @@ public:
     {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count();
     }
-    void idle_until(double t) override
-    {
-        // completions are polled, so never sleep long
-        const double dt = std::min(t - now(), 20e-6);
-        if (dt > 2e-6) std::this_thread::sleep_for(std::chrono::duration<double>(dt));
-        else std::this_thread::yield();
-    }
+    void idle_until(double t) override { idle_wait(t - now(), false); }
     char *base() override { return base_; }
     int admit(const Req &r) override
     {
@@ -615,9 +619,8 @@ struct QueueRes {
     int *done_h = nullptr, *done_d = nullptr;
     QDev *dev = nullptr;
     size_t dev_bytes = 0;
-    hipStream_t ks = nullptr, cs = nullptr;   // kernel, copies
+    hipStream_t ks = nullptr, cs = nullptr;   // kernel, result copies
     hipEvent_t kev = nullptr;                 // kernel instance finished
-    std::vector<hipEvent_t> cev;              // per slot: operand copies finished
 
     int init(const serve_config &cfg, int64_t ring)
     {
@@ -635,14 +638,11 @@ struct QueueRes {
         if ((e = hipHostGetDevicePointer((void **)&ring_d, ring_h, 0)) != hipSuccess) return fail(e);
         if ((e = hipHostGetDevicePointer((void **)&ctl_d, ctl_h, 0)) != hipSuccess) return fail(e);
         if ((e = hipHostGetDevicePointer((void **)&done_d, done_h, 0)) != hipSuccess) return fail(e);
-        dev_bytes = offsetof(QDev, counters) + (size_t)slots * sizeof(int32_t);
+        dev_bytes = offsetof(QDev, counters) + 2 * (size_t)slots * sizeof(int32_t);
         if ((e = hipMalloc((void **)&dev, dev_bytes)) != hipSuccess) return fail(e);
         if ((e = hipStreamCreateWithFlags(&ks, hipStreamNonBlocking)) != hipSuccess) return fail(e);
         if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return fail(e);
         if ((e = hipEventCreateWithFlags(&kev, hipEventDisableTiming)) != hipSuccess) return fail(e);
-        cev.assign((size_t)slots, nullptr);
-        for (auto &ev : cev)
-            if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return fail(e);
         if ((e = hipMemsetAsync(dev, 0, dev_bytes, ks)) != hipSuccess) return fail(e);
         if ((e = hipStreamSynchronize(ks)) != hipSuccess) return fail(e);
         return GEMM_OK;
@@ -650,9 +650,6 @@ struct QueueRes {
     // Frees everything; the kernel must have left (the caller synchronises).
     void free_all()
     {
-        for (auto &ev : cev)
-            if (ev) (void)hipEventDestroy(ev);
-        cev.clear();
         if (kev) (void)hipEventDestroy(kev);
         if (cs) (void)hipStreamDestroy(cs);
         if (ks) (void)hipStreamDestroy(ks);
@@ -682,6 +679,8 @@ int run_queue(const serve_config &cfg, const serve_queue_config &qc, int64_t cou
         r.a_bytes = round_up(r.in->m * r.lda * in_bytes(r.in->dtype), kAlign);
         r.b_bytes = round_up(r.in->k * r.ldb * in_bytes(r.in->dtype), kAlign);
         r.qtiles = queue_tiles(*r.in);
+        r.qcopies = (r.in->m * r.lda * in_bytes(r.in->dtype) + kCopyChunk - 1) / kCopyChunk +
+                    (r.in->k * r.ldb * in_bytes(r.in->dtype) + kCopyChunk - 1) / kCopyChunk;
     }
     std::vector<int64_t> order((size_t)count);
     for (int64_t i = 0; i < count; ++i) order[(size_t)i] = i;
@@ -690,7 +689,9 @@ int run_queue(const serve_config &cfg, const serve_queue_config &qc, int64_t cou
 
     const int64_t ring = qc.ring_tiles > 0 ? qc.ring_tiles : kRingDefault;
     const int64_t idle = qc.idle_polls > 0 ? qc.idle_polls : kIdleDefault;
-    const int grid = qc.workgroups > 0 ? qc.workgroups : cus;
+    // at most one workgroup per compute unit: the result copies (and any
+    // other work on the device) need the rest of each unit's registers
+    const int grid = qc.workgroups > 0 ? std::min(qc.workgroups, cus) : cus;
     QueueRes q;
     int rc = q.init(cfg, ring);
     if (rc != GEMM_OK) {
@@ -705,7 +706,8 @@ int run_queue(const serve_config &cfg, const serve_queue_config &qc, int64_t cou
     int64_t launches = 0;
     bool running = false;
     auto launch = [&]() {
-        int r2 = launch_queue_kernel(q.ring_d, ring - 1, q.ctl_d, q.done_d, q.dev, idle, grid, q.ks);
+        int r2 = launch_queue_kernel(q.ring_d, ring - 1, q.ctl_d, q.done_d, q.dev, cfg.max_active, idle,
+                                     grid, q.ks);
         if (r2 == GEMM_OK && hipEventRecord(q.kev, q.ks) != hipSuccess) r2 = GEMM_E_HIP;
         if (r2 == GEMM_OK) {
             ++launches;
@@ -717,7 +719,7 @@ int run_queue(const serve_config &cfg, const serve_queue_config &qc, int64_t cou
 
     Arena arena;
     arena.init(cfg.budget_bytes);
-    std::deque<int64_t> queue, copying;
+    std::deque<int64_t> queue;
     std::vector<int64_t> published;
     std::vector<int> free_slots, slot_gen((size_t)cfg.max_active, 0);
     for (int i = cfg.max_active - 1; i >= 0; --i) free_slots.push_back(i);
@@ -742,15 +744,17 @@ int run_queue(const serve_config &cfg, const serve_queue_config &qc, int64_t cou
         bool progressed = false;
         while (next_arrival < order.size() && reqs[order[next_arrival]].arrival_s <= now)
             queue.push_back(order[next_arrival++]);
-        // admission: FIFO; the operands are copied into the arena on the copy stream
+        // admission: FIFO; a request is published at once, its operand copies
+        // as the first tiles
         while (!queue.empty() && !free_slots.empty()) {
             Req &r = R[(size_t)queue.front()];
-            if (round_up(r.bytes, kAlign) > cfg.budget_bytes || r.qtiles > ring) {
+            if (round_up(r.bytes, kAlign) > cfg.budget_bytes || r.qtiles + r.qcopies > ring) {
                 r.status = GEMM_E_WORKSPACE;
                 queue.pop_front();
                 finish(r);
                 continue;
             }
+            if (tail + r.qtiles + r.qcopies - completed_tiles > ring) break;   // ring full
             const int64_t off = arena.alloc(r.bytes);
             if (off < 0) break;
             queue.pop_front();
@@ -759,34 +763,22 @@ int run_queue(const serve_config &cfg, const serve_queue_config &qc, int64_t cou
             r.qslot = free_slots.back();
             free_slots.pop_back();
             peak_active = std::max(peak_active, ++active);
+            r.qgen = ++slot_gen[(size_t)r.qslot];
             const int es = in_bytes(r.in->dtype);
-            hipError_t e = hipMemcpyAsync(q.base + r.off, r.in->a_src, (size_t)(r.in->m * r.lda * es),
-                                          hipMemcpyDeviceToDevice, q.cs);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(q.base + r.off + r.a_bytes, r.in->b_src,
-                                   (size_t)(r.in->k * r.ldb * es), hipMemcpyDeviceToDevice, q.cs);
-            if (e == hipSuccess) e = hipEventRecord(q.cev[(size_t)r.qslot], q.cs);
-            if (e != hipSuccess) {
-                t_tls.hip_err = (int)e;
-                r.failed = true;
-                r.status = GEMM_E_SERVE;
-                finish(r);
-                continue;
-            }
-            copying.push_back(r.idx);
-            progressed = true;
-        }
-        // publication: requests whose operands have landed, while the ring has room
-        while (!copying.empty()) {
-            Req &r = R[(size_t)copying.front()];
-            const hipError_t e = hipEventQuery(q.cev[(size_t)r.qslot]);
-            if (e == hipErrorNotReady) break;
-            if (e != hipSuccess) {
-                t_tls.hip_err = (int)e;
-                result = GEMM_E_SERVE;
-                break;
-            }
-            if (tail + r.qtiles - completed_tiles > ring) break;
+            int64_t pos = tail;
+            auto put_copies = [&](const void *src, char *dst, int64_t bytes) {
+                for (int64_t o = 0; o < bytes; o += kCopyChunk) {
+                    QTile &rec = q.ring_h[pos++ & (ring - 1)];
+                    std::memset(&rec, 0, sizeof rec);
+                    rec.a.A = (const char *)src + o;
+                    rec.a.C = dst + o;
+                    rec.a.lda = std::min(kCopyChunk, bytes - o);
+                    rec.slot = r.qslot;
+                    rec.kind = 1;
+                }
+            };
+            put_copies(r.in->a_src, q.base + r.off, r.in->m * r.lda * es);
+            put_copies(r.in->b_src, q.base + r.off + r.a_bytes, r.in->k * r.ldb * es);
             int64_t mc = 128, nc = 128;
             queue_tiles(*r.in, &mc, &nc);
             const int kclass = kclass_of(r.in->dtype, r.in->k);
@@ -810,24 +802,28 @@ int run_queue(const serve_config &cfg, const serve_queue_config &qc, int64_t cou
             a.order = 0;
             a.group = 8;
             a.terms = split_terms(kclass);
-            r.qgen = ++slot_gen[(size_t)r.qslot];
             for (int64_t t = 0; t < r.qtiles; ++t) {
-                QTile &rec = q.ring_h[(tail + t) & (ring - 1)];
+                QTile &rec = q.ring_h[pos++ & (ring - 1)];
                 rec.a = a;
                 rec.t = (int)t;
                 rec.slot = r.qslot;
                 rec.ntiles = (int)r.qtiles;
                 rec.body = kclass;
                 rec.gen = r.qgen;
+                rec.kind = 0;
+                rec.ncopy = (int)r.qcopies;
+                rec.pad = 0;
             }
-            tail += r.qtiles;
+            tail = pos;
             __atomic_store_n(&q.ctl_h->tail, tail, __ATOMIC_RELEASE);
             r.publish_t = now_s();
             published.push_back(r.idx);
-            copying.pop_front();
             progressed = true;
         }
-        if (result != GEMM_OK) break;
+        if (__atomic_load_n(&q.ctl_h->fault, __ATOMIC_ACQUIRE)) {
+            result = GEMM_E_SERVE;
+            break;
+        }
         // completions, in any order
         for (size_t i = 0; i < published.size();) {
             Req &r = R[(size_t)published[i]];
@@ -844,7 +840,7 @@ int run_queue(const serve_config &cfg, const serve_queue_config &qc, int64_t cou
                         r.status = GEMM_E_SERVE;
                     }
                 }
-                completed_tiles += r.qtiles;
+                completed_tiles += r.qtiles + r.qcopies;
                 finish(r);
                 published[i] = published.back();
                 published.pop_back();
@@ -879,11 +875,8 @@ int run_queue(const serve_config &cfg, const serve_queue_config &qc, int64_t cou
             progressed = true;
         }
         if (!progressed) {
-            // completions are polled, so never sleep long
-            double dt = 20e-6;
-            if (next_arrival < order.size()) dt = std::min(dt, reqs[order[next_arrival]].arrival_s - now);
-            if (dt > 2e-6) std::this_thread::sleep_for(std::chrono::duration<double>(dt));
-            else std::this_thread::yield();
+            const double dt = next_arrival < order.size() ? reqs[order[next_arrival]].arrival_s - now : 1.0;
+            idle_wait(dt, !published.empty() || !queue.empty());
         }
     }
     // the kernel leaves on the stop word (or, at the latest, after its idle bound)
