@@ -235,7 +235,8 @@ def extras(mg, torch, stream, ops):
 
 
 def precision_8192(mg, torch, stream):
-    """8192^3 in every precision path, N(0,1) inputs (INT8 uniform)."""
+    """8192^3 in every precision path, N(0,1) inputs (INT8 uniform); FP64
+    against its own MFMA peak (78.6 TFLOP/s)."""
     from paper_2310_20347_amd import inputs
     n = 8192
     a32 = inputs.normal((n, n), inputs.seed_for(3, "A"))
@@ -262,6 +263,14 @@ def precision_8192(mg, torch, stream):
         prec[name] = {"ms": round(ms, 3), "tflops": round(tf, 1),
                       "mfma_util": round(terms * tf / peak, 4)}
         del Ad, Bd
+    a64 = torch.from_numpy(inputs.normal((n, n), inputs.seed_for(3, "A"), dtype=np.float64)).cuda()
+    b64 = torch.from_numpy(inputs.normal((n, n), inputs.seed_for(3, "B"), dtype=np.float64)).cuda()
+    C64 = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    ms = _time_call(lambda: mg.gemm("N", "N", n, n, n, 1.0, a64, n, b64, n, 0.0, C64, n, mg.GEMM_F64,
+                                    stream=stream), torch, stream)
+    prec["f64"] = {"ms": round(ms, 3), "tflops": round(2.0 * n ** 3 / ms / 1e9, 1),
+                   "mfma_util": round(2.0 * n ** 3 / ms / 1e9 / 78.6, 4)}
+    del a64, b64, C64
     ai = torch.from_numpy(inputs.int8_uniform((n, n), 41)).cuda()
     bi = torch.from_numpy(inputs.int8_uniform((n, n), 42)).cuda()
     Ci = torch.empty((n, n), dtype=torch.int32, device="cuda")

@@ -26,10 +26,12 @@
  *   GEMM_F16:           A, B IEEE binary16;                   C float32
  *   GEMM_F8E4M3:        A, B OCP FP8 E4M3FN bytes;            C float32
  *   GEMM_I8:            A, B int8;                            C int32
- *   Accumulation is FP32 for every float type and INT32 for GEMM_I8.
- *   alpha and beta are passed as double and used as float32 by the float
- *   paths; for GEMM_I8 they must be integers representable in int32 and the
- *   epilogue wraps modulo 2^32 (two's complement).
+ *   GEMM_F64:           A, B float64;                         C float64
+ *   Accumulation is FP32 for the float types up to FP32, FP64 for GEMM_F64
+ *   and INT32 for GEMM_I8.  alpha and beta are passed as double, used as
+ *   float32 by the FP32-output paths and as double by GEMM_F64; for GEMM_I8
+ *   they must be integers representable in int32 and the epilogue wraps
+ *   modulo 2^32 (two's complement).
  * Pointers: A, B, C are DEVICE pointers owned by the caller, aligned at least
  *   to their element size.  The library never frees or retains them.
  * Semantics (BLAS):
@@ -66,7 +68,11 @@ typedef enum {
     GEMM_I8 = 5,              /* int8 inputs, int32 accumulate, bit-exact                  */
     GEMM_F32_BF16X3_ONLY = 6, /* split product, always 3 terms (hi*hi, hi*mid, mid*hi)     */
     GEMM_F32_BF16X6 = 7,      /* split product, always 6 terms (adds mid*mid, hi*lo, lo*hi)*/
-    GEMM_NUM_DTYPES = 8
+    GEMM_F64 = 8,             /* FP64 inputs, FP64 accumulate (v_mfma_f64_16x16x4f64) and  */
+                              /* FP64 C; alpha and beta used in full double precision;     */
+                              /* gemm() only (the grouped and serving paths return         */
+                              /* GEMM_E_UNSUPPORTED / reject it)                           */
+    GEMM_NUM_DTYPES = 9
 } gemm_dtype;
 
 enum {

@@ -110,7 +110,7 @@ int serve_run(const serve_config *cfg, int64_t count, const serve_request *reqs,
  */
 typedef struct {
     int64_t ring_tiles;   /* tile records in the ring: a power of two in          */
-                          /* [1024, 2^24], or 0 for 65536 (128 bytes each)        */
+                          /* [1024, 2^24], or 0 for 65536 (144 bytes each)        */
     int workgroups;       /* persistent workgroups, 0 = one per compute unit;      */
                           /* larger values are reduced to that                     */
     int64_t idle_polls;   /* empty polls before the kernel leaves, 0 = 20000       */

@@ -16,10 +16,11 @@ GEMM_F8E4M3 = 4
 GEMM_I8 = 5
 GEMM_F32_BF16X3_ONLY = 6
 GEMM_F32_BF16X6 = 7
-GEMM_NUM_DTYPES = 8
+GEMM_F64 = 8
+GEMM_NUM_DTYPES = 9
 DTYPE_NAMES = {GEMM_F32: "f32", GEMM_F32_BF16X3: "bf16x3", GEMM_BF16: "bf16", GEMM_F16: "f16",
                GEMM_F8E4M3: "e4m3", GEMM_I8: "i8", GEMM_F32_BF16X3_ONLY: "bf16x3_only",
-               GEMM_F32_BF16X6: "bf16x6"}
+               GEMM_F32_BF16X6: "bf16x6", GEMM_F64: "f64"}
 
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64

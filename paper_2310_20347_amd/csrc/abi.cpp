@@ -51,6 +51,7 @@ int kclass_of(int dtype, int64_t k)
     case GEMM_F16: return K_F16;
     case GEMM_F8E4M3: return K_F8;
     case GEMM_I8: return K_I8;
+    case GEMM_F64: return K_F64;
     default: return -1;
     }
 }
@@ -60,6 +61,7 @@ int elem_bytes(int kclass)
     switch (kclass) {
     case K_F32: case K_SPLIT2: case K_SPLIT3: return 4;
     case K_BF16: case K_F16: return 2;
+    case K_F64: return 8;
     default: return 1;
     }
 }
@@ -107,7 +109,7 @@ int validate(char ta, char tb, int64_t m, int64_t n, int64_t k, double alpha, co
     if (is_int && !int32_exact(beta)) return -11;
     const bool write = m > 0 && n > 0 && !((alpha == 0.0 || k == 0) && beta == 1.0);
     if (write && C == nullptr) return -12;
-    if (C != nullptr && (reinterpret_cast<uintptr_t>(C) % 4) != 0) return -12;
+    if (C != nullptr && (reinterpret_cast<uintptr_t>(C) % (dtype == GEMM_F64 ? 8 : 4)) != 0) return -12;
     if (ldc < std::max<int64_t>(1, n)) return -13;
     return 0;
 }
@@ -167,6 +169,7 @@ void ensure_registered()
     register_nopack(g_cfgs);
     // split product on direct-staged FP32 panels
     register_splitdirect(g_cfgs);
+    register_f64(g_cfgs);
     for (size_t i = 0; i < g_cfgs.size(); ++i) g_by_class[g_cfgs[i].kclass].push_back((int)i);
     g_registered = true;
 }
@@ -559,6 +562,8 @@ int plan_gemm(int dtype, char ta, char tb, int64_t m, int64_t n, int64_t k, doub
     a.order = order;
     a.group = std::max(1, group);
     a.terms = split_terms(kclass);
+    a.dalpha = alpha;
+    a.dbeta = beta;
     return reg;
 }
 
@@ -582,7 +587,7 @@ int gemm(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha
     if (rc != GEMM_OK) return rc;
     hipStream_t s = t_tls.stream;
     if (alpha == 0.0 || k == 0) {
-        launch_scale(C, ldc, (int)m, (int)n, beta, dtype == GEMM_I8, s);
+        launch_scale(C, ldc, (int)m, (int)n, beta, dtype == GEMM_I8 ? 1 : (dtype == GEMM_F64 ? 2 : 0), s);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) {
             t_tls.hip_err = (int)e;

@@ -14,10 +14,12 @@
 namespace mg {
 
 typedef unsigned int u32;
+typedef unsigned long long u64;
 typedef u32 u32x2 __attribute__((ext_vector_type(2)));
 typedef u32 u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
@@ -36,6 +38,7 @@ struct GemmArgs {
     int order;              // 0: B3A2C0 raster (column panels outer), 1: A3B2C0
     int group;              // raster group width, in tiles
     int terms;              // split-product terms (3 or 6) for the split path
+    double dalpha, dbeta;   // FP64 path
 };
 
 // --------------------------------------------------------------------------
@@ -65,6 +68,12 @@ struct TI8 {
     static constexpr int GES = 1, LES = 1, PLANES = 1, FDW = 4, KF = 64, MNV = 4;
     static constexpr bool INT = true, SPLIT = false;
 };
+// FP64: v_mfma_f64_16x16x4f64, one double per lane and k step; a 16-byte
+// fragment read holds two k steps.
+struct TF64 {
+    static constexpr int GES = 8, LES = 8, PLANES = 1, FDW = 4, KF = 8, MNV = 2;
+    static constexpr bool INT = false, SPLIT = false;
+};
 struct TF8 {
     static constexpr int GES = 1, LES = 1, PLANES = 1, FDW = 8, KF = 128, MNV = 4;
     static constexpr bool INT = false, SPLIT = false;
@@ -89,6 +98,19 @@ template <>
 struct AccOf<TI8> {
     typedef i32x4 type;
 };
+template <>
+struct AccOf<TF64> {
+    typedef f64x4 type;
+};
+
+// The BLAS alpha of a tile's arguments is non-zero (the k loop runs).
+template <class DT>
+__device__ __forceinline__ bool alpha_nonzero(const GemmArgs &p)
+{
+    if constexpr (DT::INT) return p.ialpha != 0;
+    else if constexpr (DT::GES == 8) return p.dalpha != 0.0;
+    else return p.alpha != 0.0f;
+}
 
 // --------------------------------------------------------------------------
 // LDS panel layout.  An operand panel (the packed Ac or Bc of one stage) is

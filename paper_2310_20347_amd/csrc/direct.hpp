@@ -254,6 +254,15 @@ __device__ __forceinline__ void read_frag_tr(const char *panel, int r0, int c, i
             const int kr = c * DT::KF + 4 * g + d;
             f[0][d] = *(const u32 *)(panel + mn_off<4, RB, 8>(kr, (r0 + s) * 4));
         }
+    } else if constexpr (GES == 8) {
+        // FP64: lane group g holds k rows c*KF + 2g and 2g+1, one 64-bit read each
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int kr = c * DT::KF + 2 * g + e;
+            const u32x2 v = *(const u32x2 *)(panel + mn_off<8, RB, 8>(kr, (r0 + s) * 8));
+            f[0][2 * e] = v[0];
+            f[0][2 * e + 1] = v[1];
+        }
     } else if constexpr (GES == 2) {
         // two reads of 4 k values: lane s addresses k row 4h + s/4, elements 4*(s%4)..+3
 #pragma unroll
@@ -356,7 +365,7 @@ struct DTile {
 #pragma unroll
             for (int j = 0; j < FN; ++j) acc[i][j] = Acc{0, 0, 0, 0};
 
-        const bool form = p.k > 0 && (DT::INT ? p.ialpha != 0 : p.alpha != 0.0f);
+        const bool form = p.k > 0 && alpha_nonzero<DT>(p);
         const int nk = form ? (p.k + KC - 1) / KC : 0;
         if (nk > 0) {
             const char *A = (const char *)p.A;

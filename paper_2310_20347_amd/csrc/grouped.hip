@@ -170,6 +170,7 @@ static int build_table(const GroupedDev *gd, int cus, int64_t count, const gemm_
     if (count > 0 && !pr) return -2;
     if (count > kCapacity) return GEMM_E_WORKSPACE;
     const int fam = family_of(dtype);
+    if (fam < 0) return GEMM_E_UNSUPPORTED;
     const GroupedFamily &F = gd->fam[fam];
     for (int64_t p = 0; p < count; ++p) {
         const gemm_problem &q = pr[p];
@@ -298,6 +299,7 @@ int gemm_grouped(int64_t count, const gemm_problem *problems, int dtype)
     if (count < 0) return -1;
     if (count > 0 && !problems) return -2;
     if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -3;
+    if (family_of(dtype) < 0) return GEMM_E_UNSUPPORTED;
     if (count > kCapacity) return GEMM_E_WORKSPACE;
     // validate before touching the device (same rules as gemm)
     for (int64_t p = 0; p < count; ++p) {
@@ -375,6 +377,7 @@ int gemm_grouped_slot_write(void *slot, int64_t count, const gemm_problem *probl
     Slot *s = (Slot *)slot;
     if (count > s->capacity) return GEMM_E_WORKSPACE;
     const int fam = family_of(dtype);
+    if (fam < 0) return GEMM_E_UNSUPPORTED;
     if (s->family >= 0 && s->family != fam) return GEMM_E_UNSUPPORTED;
     DevState *d = nullptr;
     int rc = ensure_grouped(&d);

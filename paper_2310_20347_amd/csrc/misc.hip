@@ -30,16 +30,30 @@ __global__ void scale_i32_kernel(int *C, int64_t ldc, int m, int n, int beta)
     }
 }
 
-void launch_scale(void *C, int64_t ldc, int m, int n, double beta, bool is_int, hipStream_t s)
+__global__ void scale_f64_kernel(double *C, int64_t ldc, int m, int n, double beta)
+{
+    const int64_t total = (int64_t)m * n;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / n, j = t - i * n;
+        double *c = C + i * ldc + j;
+        *c = beta == 0.0 ? 0.0 : beta * *c;   // beta == 0: C is not read
+    }
+}
+
+void launch_scale(void *C, int64_t ldc, int m, int n, double beta, int elem, hipStream_t s)
 {
     const int64_t total = (int64_t)m * n;
     const int threads = 256;
     int64_t blocks = (total + threads - 1) / threads;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
-    if (is_int)
+    if (elem == 1)
         hipLaunchKernelGGL(scale_i32_kernel, dim3((unsigned)blocks), dim3(threads), 0, s,
                            (int *)C, ldc, m, n, (int)beta);
+    else if (elem == 2)
+        hipLaunchKernelGGL(scale_f64_kernel, dim3((unsigned)blocks), dim3(threads), 0, s,
+                           (double *)C, ldc, m, n, beta);
     else
         hipLaunchKernelGGL(scale_f32_kernel, dim3((unsigned)blocks), dim3(threads), 0, s,
                            (float *)C, ldc, m, n, (float)beta);
@@ -106,7 +120,7 @@ __device__ __forceinline__ uint32_t mix(uint64_t x)
 
 // Fills `count` elements of `es` bytes with finite values in [-1, 1]
 // (float formats) or arbitrary bytes (int8).  kind: 0 f32, 1 bf16, 2 f16,
-// 3 e4m3, 4 int8.
+// 3 e4m3, 4 int8, 5 f64.
 __global__ void fill_kernel(void *p, int64_t count, int kind, uint32_t seed)
 {
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count;
@@ -118,6 +132,7 @@ __global__ void fill_kernel(void *p, int64_t count, int kind, uint32_t seed)
         case 1: ((__bf16 *)p)[t] = (__bf16)v; break;
         case 2: ((_Float16 *)p)[t] = (_Float16)v; break;
         case 3: ((uint8_t *)p)[t] = (uint8_t)(h & 0xB7u); break;  // exponent <= 6: |x| < 2
+        case 5: ((double *)p)[t] = (double)v; break;
         default: ((int8_t *)p)[t] = (int8_t)(h & 0xFFu); break;
         }
     }

@@ -130,7 +130,7 @@ struct UTile {
 #pragma unroll
             for (int j = 0; j < FN; ++j) acc[i][j] = Acc{0, 0, 0, 0};
 
-        const bool form = p.k > 0 && (DT::INT ? p.ialpha != 0 : p.alpha != 0.0f);
+        const bool form = p.k > 0 && alpha_nonzero<DT>(p);
         const int nk = form ? (p.k + KC - 1) / KC : 0;
         if (nk > 0) {
             const char *A = (const char *)p.A;

@@ -1,7 +1,7 @@
 // Persistent request-queue kernel (device side of serve_run_queue).
 //
 // Each workgroup loops: claim the next tile index, wait until the host has
-// published it, copy its 128-byte record into LDS, and run it.  A copy tile
+// published it, copy its 144-byte record into LDS, and run it.  A copy tile
 // moves one chunk of a request's operands into the arena and counts itself
 // in the slot's copy counter.  An output tile waits for that counter to
 // reach the request's copy tiles, then runs the tile body of the request's
@@ -134,7 +134,8 @@ __global__ void __launch_bounds__(256, 2) queue_kernel(const QTile *ring, int64_
         const int64_t t = s_t;
         if (t < 0) break;
         // the record is in fine-grained host memory, read uncached
-        if (tid < 8) ((u32x4 *)&s_tile)[tid] = ((const u32x4 *)(ring + (t & ring_mask)))[tid];
+        if (tid < (int)(sizeof(QTile) / 16))
+            ((u32x4 *)&s_tile)[tid] = ((const u32x4 *)(ring + (t & ring_mask)))[tid];
         __syncthreads();
         const GemmArgs p = s_tile.a;
         const int slot = s_tile.slot;

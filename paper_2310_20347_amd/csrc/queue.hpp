@@ -20,7 +20,7 @@
 
 namespace mg {
 
-// One published unit of work (128 bytes, copied into LDS by 8 lanes):
+// One published unit of work (144 bytes, copied into LDS by 9 lanes):
 //   kind 1, a copy tile: a.lda bytes from a.A to a.C (a request's operands
 //     materialised in the arena at admission, in chunks of kCopyChunk);
 //   kind 0, an output tile: the request's arguments and the tile's index in
@@ -37,7 +37,7 @@ struct QTile {
     int pad;
 };
 constexpr int64_t kCopyChunk = 256 << 10;   // bytes per copy tile
-static_assert(sizeof(QTile) == 128, "tile records are 128 bytes");
+static_assert(sizeof(QTile) == 144, "tile records are 144 bytes");
 
 // Control words in pinned host memory: tail and stop written by the host,
 // fault by the kernel.

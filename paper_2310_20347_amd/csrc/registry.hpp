@@ -18,7 +18,7 @@
 namespace mg {
 
 // Kernel dtype classes (the ABI's split dtype maps to SPLIT2 or SPLIT3).
-enum KClass { K_F32 = 0, K_SPLIT2, K_SPLIT3, K_BF16, K_F16, K_F8, K_I8, K_NUM };
+enum KClass { K_F32 = 0, K_SPLIT2, K_SPLIT3, K_BF16, K_F16, K_F8, K_I8, K_F64, K_NUM };
 
 struct KernelCfg {
     int kclass = 0;
@@ -55,9 +55,10 @@ void register_direct_half(std::vector<KernelCfg> &out);
 void register_direct_byte(std::vector<KernelCfg> &out);
 void register_nopack(std::vector<KernelCfg> &out);
 void register_splitdirect(std::vector<KernelCfg> &out);
+void register_f64(std::vector<KernelCfg> &out);
 
-// Plain C = beta * C (alpha == 0 or k == 0), float or int32 elements.
-void launch_scale(void *C, int64_t ldc, int m, int n, double beta, bool is_int, hipStream_t s);
+// Plain C = beta * C (alpha == 0 or k == 0); elem: 0 float, 1 int32, 2 double.
+void launch_scale(void *C, int64_t ldc, int m, int n, double beta, int elem, hipStream_t s);
 
 // Split-K reduction: C = alpha * sum_{s < S} P[s] + beta * C, slices summed in
 // order (P: S partial m x n tiles, row stride n, float or int32).

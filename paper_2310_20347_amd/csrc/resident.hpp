@@ -167,7 +167,7 @@ struct ResidentTile {
                 cstore(p, cc, m0, n0, bi_of(rb, ob), bj_of(rb, ob), lane, z);
             }
 
-        const bool form = p.k > 0 && (DT::INT ? p.ialpha != 0 : p.alpha != 0.0f);
+        const bool form = p.k > 0 && alpha_nonzero<DT>(p);
         const int nk = form ? (p.k + KC - 1) / KC : 0;
         const char *Pm = (const char *)(AR ? p.B : p.A);
         const int64_t pld = AR ? p.ldb : p.lda;

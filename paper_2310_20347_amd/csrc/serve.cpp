@@ -330,7 +330,7 @@ int check_requests(int64_t count, const serve_request *reqs, bool need_src)
     for (int64_t i = 0; i < count; ++i) {
         const serve_request &r = reqs[i];
         if (r.m <= 0 || r.n <= 0 || r.k <= 0 || r.m > 0x7FFFFFFF || r.n > 0x7FFFFFFF ||
-            r.k > 0x7FFFFFFF || r.dtype < 0 || r.dtype >= GEMM_NUM_DTYPES ||
+            r.k > 0x7FFFFFFF || r.dtype < 0 || r.dtype >= GEMM_F64 ||
             !std::isfinite(r.arrival_s) || r.arrival_s < 0 ||
             (need_src && (!r.a_src || !r.b_src)))
             return -3;

@@ -329,7 +329,8 @@ __device__ __forceinline__ void pin_order()
 // ---------------------------------------------------------------------------
 template <class DT>
 struct Sub {
-    static constexpr int value = DT::SPLIT ? (DT::PLANES == 2 ? 3 : 6) : (DT::GES == 4 ? 4 : 1);
+    static constexpr int value =
+        DT::SPLIT ? (DT::PLANES == 2 ? 3 : 6) : (DT::GES == 4 ? 4 : (DT::GES == 8 ? 2 : 1));
 };
 
 template <class DT>
@@ -346,6 +347,11 @@ __device__ __forceinline__ void mma_step(typename AccOf<DT>::type &acc, const u3
         u32x4 xv = {x[0], x[1], x[2], x[3]}, yv = {y[0], y[1], y[2], y[3]};
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, xv),
                                                       __builtin_bit_cast(bf16x8, yv), acc, 0, 0, 0);
+    } else if constexpr (DT::GES == 8) {  // FP64: k step s of two
+        const u64 x = ((u64)a[0][2 * s + 1] << 32) | a[0][2 * s];
+        const u64 y = ((u64)b[0][2 * s + 1] << 32) | b[0][2 * s];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(__builtin_bit_cast(double, x),
+                                                   __builtin_bit_cast(double, y), acc, 0, 0, 0);
     } else if constexpr (DT::GES == 4) {  // plain FP32: k step s of four
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__builtin_bit_cast(float, a[0][s]),
                                                   __builtin_bit_cast(float, b[0][s]), acc, 0, 0, 0);
@@ -395,7 +401,7 @@ __device__ __forceinline__ void read_frag(const char *planes, int plane_bytes, i
 // Epilogue of a wave's FM x FN accumulator blocks whose top-left corner is
 // (r0, c0): C = alpha * acc + beta * C (C not read when beta == 0; INT8
 // wraps modulo 2^32).  Accumulator layout: lane l, register r -> row
-// 4*(l/16)+r, column l%16 of the block.
+// 4*(l/16)+r (FP64: l/16+4r), column l%16 of the block.
 // ---------------------------------------------------------------------------
 template <class DT, int FM, int FN>
 __device__ __forceinline__ void store_c(const GemmArgs &p, const typename AccOf<DT>::type (*acc)[FN],
@@ -409,13 +415,21 @@ __device__ __forceinline__ void store_c(const GemmArgs &p, const typename AccOf<
         for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = rbase + 16 * i + r, col = cbase + 16 * j;
+                // the FP64 MFMA interleaves its rows: register r of lane l is
+                // row l/16 + 4r (measured with identity operands)
+                const int row = DT::GES == 8 ? r0 + 16 * i + (lane >> 4) + 4 * r : rbase + 16 * i + r;
+                const int col = cbase + 16 * j;
                 if (row < p.m && col < p.n) {
                     if constexpr (DT::INT) {
                         int *c = (int *)p.C + (int64_t)row * p.ldc + col;
                         u32 v = (u32)p.ialpha * (u32)acc[i][j][r];
                         if (p.ibeta != 0) v += (u32)p.ibeta * (u32)(*c);
                         *c = (int)v;
+                    } else if constexpr (DT::GES == 8) {
+                        double *c = (double *)p.C + (int64_t)row * p.ldc + col;
+                        double v = p.dalpha * acc[i][j][r];
+                        if (p.dbeta != 0.0) v = __builtin_fma(p.dbeta, *c, v);
+                        *c = v;
                     } else {
                         float *c = (float *)p.C + (int64_t)row * p.ldc + col;
                         float v = p.alpha * acc[i][j][r];
@@ -491,7 +505,7 @@ struct Tile {
 #pragma unroll
             for (int j = 0; j < FN; ++j) acc[i][j] = Acc{0, 0, 0, 0};
 
-        const bool form = p.k > 0 && (DT::INT ? p.ialpha != 0 : p.alpha != 0.0f);
+        const bool form = p.k > 0 && alpha_nonzero<DT>(p);
         const int nk = form ? (p.k + KC - 1) / KC : 0;
         const char *A = (const char *)p.A;
         const char *B = (const char *)p.B;

@@ -32,6 +32,7 @@ static int fill_kind(int kclass)
     case K_BF16: return 1;
     case K_F16: return 2;
     case K_F8: return 3;
+    case K_F64: return 5;
     default: return 4;
     }
 }
@@ -64,7 +65,7 @@ extern "C" int gemm_tune(int dtype, int64_t count, const int64_t *shapes, int re
         const int es = elem_bytes(kclass_of(dtype, k));
         maxA = std::max(maxA, size_t(m * k * es));
         maxB = std::max(maxB, size_t(k * n * es));
-        maxC = std::max(maxC, size_t(m * n * 4));
+        maxC = std::max(maxC, size_t(m * n * (dtype == GEMM_F64 ? 8 : 4)));   // C elements
     }
     void *A = nullptr, *B = nullptr, *C = nullptr;
     hipStream_t s = nullptr;

@@ -45,7 +45,7 @@ def main():
     p.add_argument("--quick", action="store_true")
     p.add_argument("--reps", type=int, default=5)
     p.add_argument("--out", default=os.path.join(HERE, "mgemm_tune.json"))
-    p.add_argument("--dtypes", default="0,1,2,3,4,5,7")
+    p.add_argument("--dtypes", default="0,1,2,3,4,5,7,8")
     a = p.parse_args()
     import torch
     torch.cuda.set_device(0)

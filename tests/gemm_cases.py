@@ -14,13 +14,13 @@ from paper_2310_20347_amd import inputs
 
 FLOAT_SPLIT = (mg.GEMM_F32_BF16X3, mg.GEMM_F32_BF16X3_ONLY, mg.GEMM_F32_BF16X6)
 ALL_DTYPES = (mg.GEMM_F32, mg.GEMM_F32_BF16X3, mg.GEMM_BF16, mg.GEMM_F16, mg.GEMM_F8E4M3,
-              mg.GEMM_I8, mg.GEMM_F32_BF16X3_ONLY, mg.GEMM_F32_BF16X6)
+              mg.GEMM_I8, mg.GEMM_F32_BF16X3_ONLY, mg.GEMM_F32_BF16X6, mg.GEMM_F64)
 
 # Graded tolerance of the normalised error max|C-Cref| / (k max|A| max|B|)
-# against the FP64 oracle on the FP32 source inputs.
+# against the FP64 oracle on the FP32 source inputs (FP64: its own inputs).
 SOURCE_TOL = {mg.GEMM_F32: 2e-6, mg.GEMM_F32_BF16X3: 2e-6, mg.GEMM_F32_BF16X6: 2e-6,
               mg.GEMM_BF16: 8e-3, mg.GEMM_F16: 8e-3, mg.GEMM_F8E4M3: 6.25e-2,
-              mg.GEMM_F32_BF16X3_ONLY: None}
+              mg.GEMM_F32_BF16X3_ONLY: None, mg.GEMM_F64: None}
 # Kernel-correctness gate: against the oracle on the inputs the kernel actually
 # multiplies, the only error left is FP32 accumulation.
 QUANT_TOL = 2e-6
@@ -34,6 +34,11 @@ def quant_tol(c):
     magnitudes exceed the source's by at most 2^-4 (1.07 covers it)."""
     if c.dtype == mg.GEMM_F8E4M3 and c.k > 0:
         return QUANT_TOL + 1.07 * 2.0 ** -11 * ((c.k + 127) // 128) / c.k
+    if c.dtype == mg.GEMM_F64:
+        # FP64 accumulation of k products, plus the alpha/beta roundings:
+        # |error| <= (k + 2) u sum|a||b| + ..., so (k + 4) u covers the
+        # normalised error with u = 2^-53
+        return (c.k + 4) * 2.0 ** -53
     return QUANT_TOL
 
 
@@ -65,6 +70,8 @@ def encode(x32, dtype):
         return inputs.to_e4m3_bits(x32)
     if dtype == mg.GEMM_I8:
         return x32.astype(np.int8)
+    if dtype == mg.GEMM_F64:
+        return np.ascontiguousarray(x32, dtype=np.float64)
     return np.ascontiguousarray(x32, dtype=np.float32)
 
 
@@ -111,21 +118,22 @@ def make_operands(c: Case):
         b = inputs.int8_uniform((c.k, c.n), s + 2).astype(np.float32)
         c0 = np.random.default_rng(s + 3).integers(-1000, 1000, size=(c.m, c.n)).astype(np.int32)
         return a, b, c0
+    ft = np.float64 if c.dtype == mg.GEMM_F64 else np.float32
     if c.dist == "uniform":
-        a = inputs.uniform((c.m, c.k), s + 1)
-        b = inputs.uniform((c.k, c.n), s + 2)
+        a = inputs.uniform((c.m, c.k), s + 1, dtype=ft)
+        b = inputs.uniform((c.k, c.n), s + 2, dtype=ft)
     elif c.dist == "normal":
-        a = inputs.normal((c.m, c.k), s + 1)
-        b = inputs.normal((c.k, c.n), s + 2)
+        a = inputs.normal((c.m, c.k), s + 1, dtype=ft)
+        b = inputs.normal((c.k, c.n), s + 2, dtype=ft)
     elif c.dist == "ints":
-        a = inputs.small_ints((c.m, c.k), s + 1)
-        b = inputs.small_ints((c.k, c.n), s + 2)
+        a = inputs.small_ints((c.m, c.k), s + 1, dtype=ft)
+        b = inputs.small_ints((c.k, c.n), s + 2, dtype=ft)
     elif c.dist == "badly_scaled":
-        a = inputs.badly_scaled(c.m, c.k, s + 1)
-        b = inputs.badly_scaled(c.k, c.n, s + 2)
+        a = inputs.badly_scaled(c.m, c.k, s + 1, dtype=ft)
+        b = inputs.badly_scaled(c.k, c.n, s + 2, dtype=ft)
     else:
         raise ValueError(c.dist)
-    c0 = inputs.uniform((c.m, c.n), s + 3)
+    c0 = inputs.uniform((c.m, c.n), s + 3, dtype=ft)
     return a, b, c0
 
 

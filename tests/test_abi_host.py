@@ -81,7 +81,7 @@ def test_null_operands_allowed_when_not_read():
 def test_strerror_and_config_introspection():
     assert "invalid" in mg.strerror(-3)
     assert mg.strerror(0) == "success"
-    for dt in range(8):
+    for dt in range(mg.GEMM_NUM_DTYPES):
         n = mg.num_configs(dt)
         assert n >= 2
         for c in range(n):
@@ -90,7 +90,7 @@ def test_strerror_and_config_introspection():
             assert info["lds_bytes"] <= 160 * 1024
             # a stage holds 128 bytes of k per panel row (64 for the deep-ring
             # direct configurations)
-            kb = info["kc"] * {0: 4, 1: 2, 2: 2, 3: 2, 4: 1, 5: 1, 6: 2, 7: 2}[dt]
+            kb = info["kc"] * {0: 4, 1: 2, 2: 2, 3: 2, 4: 1, 5: 1, 6: 2, 7: 2, 8: 8}[dt]
             assert kb == 128 or (kb == 64 and info["staging"] in ("direct", "packed"))
 
 

@@ -72,7 +72,8 @@ def test_every_configuration_and_raster_order(dtype):
 
 
 @pytest.mark.parametrize("dtype", [mg.GEMM_F32, mg.GEMM_F32_BF16X3, mg.GEMM_F32_BF16X6,
-                                   mg.GEMM_BF16, mg.GEMM_F16, mg.GEMM_F8E4M3, mg.GEMM_I8],
+                                   mg.GEMM_BF16, mg.GEMM_F16, mg.GEMM_F8E4M3, mg.GEMM_I8,
+                                   mg.GEMM_F64],
                          ids=lambda d: mg.DTYPE_NAMES[d])
 def test_every_configuration_every_layout_ragged(dtype):
     """Every configuration (register-staged, operand-resident and the LDS-ring
@@ -280,7 +281,7 @@ def test_identity_and_permutation_pins(dtype, ta, tb):
     for A in (np.eye(n, dtype=np.float32), P):
         As = stored(encode(A, dtype), ta, n)
         Bs = stored(encode(B, dtype), tb, n if tb in "Tt" else 70)
-        out_t = torch.int32 if dtype == mg.GEMM_I8 else torch.float32
+        out_t = {mg.GEMM_I8: torch.int32, mg.GEMM_F64: torch.float64}.get(dtype, torch.float32)
         dC = torch.full((n, 70), 7, dtype=out_t, device="cuda")
         mg.gemm(ta, tb, n, 70, n, 1, to_device(As), As.shape[1], to_device(Bs), Bs.shape[1], 0,
                 dC, 70, dtype)
@@ -288,14 +289,16 @@ def test_identity_and_permutation_pins(dtype, ta, tb):
         assert np.array_equal(dC.cpu().numpy(), (A @ B).astype(dC.cpu().numpy().dtype))
 
 
-@pytest.mark.parametrize("dtype", [mg.GEMM_F32, mg.GEMM_F32_BF16X3, mg.GEMM_BF16, mg.GEMM_I8])
+@pytest.mark.parametrize("dtype", [mg.GEMM_F32, mg.GEMM_F32_BF16X3, mg.GEMM_BF16, mg.GEMM_I8,
+                                   mg.GEMM_F64])
 def test_blas_special_cases(dtype):
     import torch
     is_int = dtype == mg.GEMM_I8
-    ct = torch.int32 if is_int else torch.float32
+    ct = torch.int32 if is_int else (torch.float64 if dtype == mg.GEMM_F64 else torch.float32)
     m, n, k = 37, 29, 41
     C0 = torch.arange(m * n, dtype=ct, device="cuda").reshape(m, n)
-    esz = {mg.GEMM_F32: 4, mg.GEMM_F32_BF16X3: 4, mg.GEMM_BF16: 2, mg.GEMM_I8: 1}[dtype]
+    esz = {mg.GEMM_F32: 4, mg.GEMM_F32_BF16X3: 4, mg.GEMM_BF16: 2, mg.GEMM_I8: 1,
+           mg.GEMM_F64: 8}[dtype]
     nanbuf = torch.full((m * k * 4,), -1, dtype=torch.uint8, device="cuda")  # NaN patterns
     # k == 0: C = beta * C (A, B not read)
     C = C0.clone()
@@ -309,10 +312,12 @@ def test_blas_special_cases(dtype):
     assert torch.equal(C, 3 * C0)
     # beta == 0: NaN in C is overwritten, not propagated
     if not is_int:
-        C = torch.full((m, n), float("nan"), device="cuda")
+        C = torch.full((m, n), float("nan"), dtype=ct, device="cuda")
         A = torch.ones(m * k * 4 // esz, dtype=torch.float32, device="cuda")
         if dtype == mg.GEMM_BF16:
             A = torch.ones(m * k, dtype=torch.bfloat16, device="cuda")
+        if dtype == mg.GEMM_F64:
+            A = torch.ones(m * k, dtype=torch.float64, device="cuda")
         B = torch.ones_like(A)
         mg.gemm("N", "N", m, n, k, 1, A, k, B, n, 0, C, n, dtype)
         torch.cuda.synchronize()
