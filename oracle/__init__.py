@@ -18,6 +18,8 @@ Every routine is a thin ctypes wrapper over ``oracle_gemm.c``:
                     sampled checks at sizes where the full product is too slow.
 * ``decode_*``      exact decoders for bfloat16, binary16 and OCP E4M3FN codes.
 * ``split_bf16``    round-to-nearest-even split of FP32 into bf16 pieces.
+* ``gemm_scaled``   the power-of-two scaled low-precision GEMM (per-row
+                    exponents of op(A), per-column of op(B), format codes).
 * ``normalized_error`` the graded error max|C - Cref| / (k max|A| max|B|).
 
 Storage is row-major; ``lda``/``ldb``/``ldc`` are row strides in elements.
@@ -68,9 +70,12 @@ def _load():
     lib.oracle_decode_f16.argtypes = [_P, _I64, _P]
     lib.oracle_decode_e4m3.argtypes = [_P, _I64, _P]
     lib.oracle_split_bf16.argtypes = [_P, _I64, _INT, _P, _P, _P]
+    lib.oracle_scale_exponents.argtypes = [_P, _I64, _I64, _INT, _P]
+    lib.oracle_scaled_codes.argtypes = [_P, _I64, _I64, _P, _INT, _P]
     for f in ("oracle_gemm_f64", "oracle_gemm_entries_f64", "oracle_gemm_pieces_f64",
               "oracle_gemm_i8", "oracle_gemm_entries_i8", "oracle_decode_bf16",
-              "oracle_decode_f16", "oracle_decode_e4m3", "oracle_split_bf16"):
+              "oracle_decode_f16", "oracle_decode_e4m3", "oracle_split_bf16",
+              "oracle_scale_exponents", "oracle_scaled_codes"):
         getattr(lib, f).restype = None
     _lib = lib
     return lib
@@ -248,6 +253,58 @@ def split_bf16(x, pieces):
     _load().oracle_split_bf16(_ptr(xf), xf.size, pieces, _ptr(outs[0]), _ptr(outs[1]),
                               _ptr(outs[2]))
     return [o.reshape(np.shape(x)) for o in outs[:pieces]]
+
+
+# Scaled low-precision path: format codes and the exponent T at which each
+# row's largest magnitude is placed ([2^T, 2^(T+1))).
+SCALED_FORMATS = {"bf16": (0, 0), "f16": (1, 14), "e4m3": (2, 7)}
+
+
+def scale_exponents(x, T):
+    """Per-row exponents e_r = floor(log2 max_p |x[r, p]|) - T (0 for zero or
+    non-finite rows) of a 2-D FP32 array."""
+    xf = np.ascontiguousarray(x, dtype=np.float32)
+    rows, cols = xf.shape
+    e = np.empty(rows, dtype=np.int32)
+    _load().oracle_scale_exponents(_ptr(xf), rows, cols, int(T), _ptr(e))
+    return e
+
+
+def scaled_codes(x, e, fmt):
+    """Round-to-nearest-even codes of x[r, p] * 2^-e[r] in format ``fmt``
+    ("bf16", "f16" or "e4m3"; e4m3 saturates at 448)."""
+    code, _ = SCALED_FORMATS[fmt]
+    xf = np.ascontiguousarray(x, dtype=np.float32)
+    rows, cols = xf.shape
+    ee = np.ascontiguousarray(e, dtype=np.int32)
+    out = np.empty((rows, cols), dtype=np.uint16)
+    _load().oracle_scaled_codes(_ptr(xf), rows, cols, _ptr(ee), code, _ptr(out))
+    return out.astype(np.uint8) if fmt == "e4m3" else out
+
+
+def decode_codes(codes, fmt):
+    return {"bf16": decode_bf16, "f16": decode_f16, "e4m3": decode_e4m3}[fmt](codes)
+
+
+def gemm_scaled(ta, tb, m, n, k, alpha, A, lda, B, ldb, fmt, beta=0.0, C0=None, ldc0=None):
+    """The scaled low-precision GEMM on FP32 operands: op(A) rows and op(B)
+    columns are scaled by powers of two into the format's range and rounded
+    (scale_exponents, scaled_codes); C = alpha * 2^(e_i + f_j) *
+    sum_p qa(i,p) qb(p,j) + beta * C0, evaluated in FP64 (the scalings are
+    exact there).  Returns (C, qa codes, e, qb^T codes, f)."""
+    _, T = SCALED_FORMATS[fmt]
+    A = np.asarray(A, dtype=np.float32)
+    B = np.asarray(B, dtype=np.float32)
+    opA = (A[:k, :m].T if _is_t(ta) else A[:m, :k]).astype(np.float32)
+    opBt = (B[:n, :k] if _is_t(tb) else B[:k, :n].T).astype(np.float32)   # n x k
+    e = scale_exponents(opA, T)
+    f = scale_exponents(opBt, T)
+    qa = scaled_codes(opA, e, fmt)
+    qbt = scaled_codes(opBt, f, fmt)
+    As = np.ldexp(decode_codes(qa, fmt), e[:, None].astype(np.int64))
+    Bs = np.ldexp(decode_codes(qbt, fmt), f[:, None].astype(np.int64)).T.copy()
+    C = gemm_f64("N", "N", m, n, k, alpha, As, k, Bs, n, beta, C0, ldc0)
+    return C, qa, e, qbt, f
 
 
 def normalized_error(C, Cref, k, max_a, max_b):

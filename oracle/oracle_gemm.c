@@ -24,7 +24,9 @@
  * Also here, each written from its format definition:
  *   - bfloat16 round-to-nearest-even and the hi/mid/lo split of an FP32 value
  *     into bf16 pieces (inputs of the split-product FP32-accurate path);
- *   - exact decoders for bfloat16, IEEE binary16 and OCP FP8 E4M3FN codes.
+ *   - exact decoders for bfloat16, IEEE binary16 and OCP FP8 E4M3FN codes;
+ *   - the power-of-two scaled quantisation of the scaled low-precision path
+ *     (per-row exponents, round-to-nearest-even encoders of each format).
  */
 #include <stdint.h>
 #include <string.h>
@@ -308,4 +310,90 @@ void oracle_split_bf16(const float *x, int64_t n, int pieces, uint16_t *hi,
         r = r - bf16_to_f32(md);
         lo[t] = rne_bf16(r);
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Power-of-two scaled quantisation (the scaled low-precision GEMM).         */
+/* A row r of x (rows x cols, row-major) gets the exponent                   */
+/*     e_r = floor(log2(M_r)) - T,   M_r = max_p |x[r][p]|,                   */
+/* so that M_r * 2^-e_r lies in [2^T, 2^(T+1)); e_r = 0 when M_r is zero or  */
+/* not finite.  Each value is then scaled by 2^-e_r in FP32 and rounded to   */
+/* the narrow format, to nearest, ties to even.                              */
+/* ------------------------------------------------------------------------ */
+void oracle_scale_exponents(const float *x, int64_t rows, int64_t cols, int T, int32_t *e)
+{
+    for (int64_t r = 0; r < rows; ++r) {
+        float mx = 0.0f;
+        int finite = 1;
+        for (int64_t p = 0; p < cols; ++p) {
+            const float a = fabsf(x[r * cols + p]);
+            if (!isfinite(a)) finite = 0;
+            else if (a > mx) mx = a;
+        }
+        if (!finite || mx == 0.0f) {
+            e[r] = 0;
+            continue;
+        }
+        int ex;
+        frexpf(mx, &ex);          /* mx = f * 2^ex, f in [0.5, 1) */
+        e[r] = (ex - 1) - T;
+    }
+}
+
+/* binary16, round to nearest even: subnormals are multiples of 2^-24,     */
+/* normals 1.f * 2^E with E in [-14, 15] and 10 fraction bits.             */
+static uint16_t rne_f16(float y)
+{
+    const uint16_t s = signbit(y) ? 0x8000u : 0u;
+    const float a = fabsf(y);
+    if (isnan(a)) return (uint16_t)(s | 0x7E00u);
+    if (a == 0.0f) return s;
+    if (a < 0x1p-14f) return (uint16_t)(s | (uint16_t)nearbyintf(a * 0x1p24f));
+    int ex;
+    frexpf(a, &ex);
+    int E = ex - 1;
+    const float mant = ldexpf(a, -E) - 1.0f;            /* in [0, 1), exact */
+    int q = (int)nearbyintf(mant * 1024.0f);
+    if (q == 1024) {
+        q = 0;
+        ++E;
+    }
+    if (E > 15) return (uint16_t)(s | 0x7C00u);         /* overflow: infinity */
+    return (uint16_t)(s | ((E + 15) << 10) | q);
+}
+
+/* OCP E4M3FN, round to nearest even, saturating at 448 (no infinities):   */
+/* subnormals are multiples of 2^-9, normals 1.f * 2^E, E in [-6, 8],      */
+/* 3 fraction bits.                                                          */
+static uint8_t rne_e4m3(float y)
+{
+    const uint8_t s = signbit(y) ? 0x80u : 0u;
+    const float a = fabsf(y);
+    if (isnan(a)) return (uint8_t)(s | 0x7Fu);
+    if (a == 0.0f) return s;
+    if (a < 0x1p-6f) return (uint8_t)(s | (uint8_t)nearbyintf(a * 0x1p9f));
+    int ex;
+    frexpf(a, &ex);
+    int E = ex - 1;
+    const float mant = ldexpf(a, -E) - 1.0f;
+    int q = (int)nearbyintf(mant * 8.0f);
+    if (q == 8) {
+        q = 0;
+        ++E;
+    }
+    int code = ((E + 7) << 3) | q;
+    if (E > 8 || code > 0x7E) code = 0x7E;               /* saturate to 448 */
+    return (uint8_t)(s | code);
+}
+
+/* Codes of x (rows x cols) scaled by 2^-e[r] per row.  fmt: 0 bfloat16,   */
+/* 1 binary16, 2 E4M3FN (one byte per code, stored in the low byte).       */
+void oracle_scaled_codes(const float *x, int64_t rows, int64_t cols, const int32_t *e, int fmt,
+                         uint16_t *out)
+{
+    for (int64_t r = 0; r < rows; ++r)
+        for (int64_t p = 0; p < cols; ++p) {
+            const float y = ldexpf(x[r * cols + p], -e[r]);
+            out[r * cols + p] = fmt == 0 ? rne_bf16(y) : (fmt == 1 ? rne_f16(y) : rne_e4m3(y));
+        }
 }

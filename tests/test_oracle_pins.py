@@ -350,3 +350,94 @@ def test_normalized_error_closed_form():
 def test_empty_shapes():
     assert oracle.gemm_f64("N", "N", 0, 5, 3, 1.0, np.zeros(1), 3, np.zeros(15), 5).shape == (0, 5)
     assert oracle.gemm_i8("N", "N", 4, 0, 3, 1, np.zeros(12), 3, np.zeros(1), 1).shape == (4, 0)
+
+
+# --- scaled low-precision path: exponents and format encoders --------------
+
+def _sweep_values():
+    """Magnitudes over the binary16 / E4M3 ranges incl. subnormals, exact
+    ties between neighbouring codes, and signs."""
+    rng = np.random.default_rng(17)
+    v = np.concatenate([rng.uniform(-1, 1, 4000) * np.exp2(rng.integers(-26, 16, 4000)),
+                        np.exp2(np.arange(-26, 16, dtype=np.float64)),
+                        (np.arange(1, 2048) + 0.5) * 2.0 ** -24,       # f16 subnormal ties
+                        (np.arange(1024, 2047) + 0.5) * 2.0 ** -10])   # f16 normal ties
+    return np.concatenate([v, -v]).astype(np.float32)
+
+
+def test_f16_encoder_matches_library_rounding():
+    # numpy's float32 -> float16 conversion rounds to nearest even
+    x = _sweep_values()
+    x = x[np.abs(x) < 65504]
+    codes = oracle.scaled_codes(x[None, :], np.zeros(1, np.int32), "f16")[0]
+    assert np.array_equal(codes, x.astype(np.float16).view(np.uint16))
+
+
+def test_e4m3_encoder_matches_library_rounding():
+    # torch's float32 -> float8_e4m3fn conversion rounds to nearest even in range
+    import torch
+    rng = np.random.default_rng(18)
+    x = np.concatenate([rng.uniform(-1, 1, 5000) * np.exp2(rng.integers(-11, 9, 5000)),
+                        (np.arange(1, 16) + 0.5) * 2.0 ** -9,          # subnormal ties
+                        (np.arange(8, 16) + 0.5) * 2.0 ** 4]).astype(np.float32)
+    x = x[np.abs(x) <= 448]
+    codes = oracle.scaled_codes(x[None, :], np.zeros(1, np.int32), "e4m3")[0]
+    ref = torch.from_numpy(x).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    assert np.array_equal(codes, ref)
+    # saturation, not infinity or NaN, past 448
+    big = np.array([[500.0, -1e6, 449.0]], np.float32)
+    assert list(oracle.scaled_codes(big, np.zeros(1, np.int32), "e4m3")[0]) == [0x7E, 0xFE, 0x7E]
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "f16", "e4m3"])
+def test_scale_exponents_place_each_row_max(fmt):
+    _, T = oracle.SCALED_FORMATS[fmt]
+    x = inputs.badly_scaled(40, 70, 19)
+    e = oracle.scale_exponents(x, T)
+    mx = np.max(np.abs(x), axis=1).astype(np.float64)
+    scaled = mx * np.exp2(-e.astype(np.float64))
+    assert np.all(scaled >= 2.0 ** T) and np.all(scaled < 2.0 ** (T + 1))
+    # shifting a row by 2^s shifts its exponent by s and leaves its codes alone
+    s = np.arange(-5, 35, dtype=np.int32)
+    x2 = np.ldexp(x.astype(np.float64), s[:, None]).astype(np.float32)
+    e2 = oracle.scale_exponents(x2, T)
+    assert np.array_equal(e2, e + s)
+    assert np.array_equal(oracle.scaled_codes(x2, e2, fmt), oracle.scaled_codes(x, e, fmt))
+    # zero and non-finite rows are not scaled
+    z = np.zeros((2, 5), np.float32)
+    z[1, 2] = np.inf
+    assert list(oracle.scale_exponents(z, T)) == [0, 0]
+
+
+@pytest.mark.parametrize("fmt,rel", [("bf16", 2.0 ** -8), ("f16", 2.0 ** -11), ("e4m3", 2.0 ** -4)])
+def test_scaled_codes_round_trip_within_unit_roundoff(fmt, rel):
+    _, T = oracle.SCALED_FORMATS[fmt]
+    x = inputs.normal((30, 200), 20)
+    e = oracle.scale_exponents(x, T)
+    back = np.ldexp(oracle.decode_codes(oracle.scaled_codes(x, e, fmt), fmt),
+                    e[:, None].astype(np.int64))
+    # values within the format's normal range relative to their row maximum
+    rowmax = np.max(np.abs(x), axis=1, keepdims=True)
+    normal = np.abs(x) >= rowmax * 2.0 ** -(T + 5 if fmt != "bf16" else 100)
+    err = np.abs(back - x)[normal] / np.abs(x)[normal]
+    assert err.max() <= rel
+
+
+def test_gemm_scaled_reference_equals_definition():
+    # C = alpha * diag(2^e) (Qa Qb) diag(2^f) + beta C0, with Qa, Qb the codes
+    m, n, k = 7, 5, 9
+    a = inputs.badly_scaled(m, k, 21)
+    b = inputs.badly_scaled(k, n, 22)
+    c0 = inputs.uniform((m, n), 23, dtype=np.float64)
+    C, qa, e, qbt, f = oracle.gemm_scaled("N", "N", m, n, k, 1.5, a, k, b, n, "f16", -0.5, c0, n)
+    da = oracle.decode_f16(qa) * np.exp2(e[:, None].astype(np.float64))
+    db = oracle.decode_f16(qbt) * np.exp2(f[:, None].astype(np.float64))
+    ref = np.empty((m, n))
+    for i in range(m):
+        for j in range(n):
+            ref[i, j] = 1.5 * sum(da[i, p] * db[j, p] for p in range(k)) - 0.5 * c0[i, j]
+    assert np.allclose(C, ref, rtol=1e-12, atol=0)
+    # transposed storage gives the same result
+    Ct = oracle.gemm_scaled("T", "T", m, n, k, 1.5, a.T.copy(), m, b.T.copy(), k, "f16",
+                            -0.5, c0, n)[0]
+    assert np.array_equal(C, Ct)
