@@ -263,6 +263,16 @@ def precision_8192(mg, torch, stream):
         prec[name] = {"ms": round(ms, 3), "tflops": round(tf, 1),
                       "mfma_util": round(terms * tf / peak, 4)}
         del Ad, Bd
+    # the power-of-two scaled path: FP32 operands, the product in FP16 / FP8
+    # (scaling, quantisation and epilogue passes included)
+    Ad = torch.from_numpy(a32).cuda()
+    Bd = torch.from_numpy(b32).cuda()
+    for name, dt, peak in (("f16_scaled", mg.GEMM_F16, 2516.6), ("e4m3_scaled", mg.GEMM_F8E4M3, 5033.0)):
+        ms = _time_call(lambda: mg.gemm_scaled("N", "N", n, n, n, 1.0, Ad, n, Bd, n, 0.0, Cd, n, dt,
+                                               stream=stream), torch, stream)
+        prec[name] = {"ms": round(ms, 3), "tflops": round(2.0 * n ** 3 / ms / 1e9, 1),
+                      "mfma_util": round(2.0 * n ** 3 / ms / 1e9 / peak, 4)}
+    del Ad, Bd
     a64 = torch.from_numpy(inputs.normal((n, n), inputs.seed_for(3, "A"), dtype=np.float64)).cuda()
     b64 = torch.from_numpy(inputs.normal((n, n), inputs.seed_for(3, "B"), dtype=np.float64)).cuda()
     C64 = torch.empty((n, n), dtype=torch.float64, device="cuda")

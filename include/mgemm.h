@@ -103,6 +103,27 @@ int gemm(char transA, char transB, int64_t m, int64_t n, int64_t k,
          double alpha, const void *A, int64_t lda, const void *B, int64_t ldb,
          double beta, void *C, int64_t ldc, int dtype);
 
+/*
+ * Power-of-two scaled low-precision GEMM on FP32 operands (A, B, C float32,
+ * the layouts and BLAS semantics of gemm()).  Each row i of op(A) and each
+ * column j of op(B) is scaled by 2^-e_i, 2^-f_j so that its largest
+ * magnitude M lands in [2^T, 2^(T+1)) (e = floor(log2 M) - T; rows that are
+ * zero or hold Inf/NaN: e = 0), rounded to the format of `dtype` (nearest,
+ * ties to even; E4M3 saturates at 448) and multiplied by that format's GEMM
+ * (FP32 accumulation); then C = alpha * 2^(e_i + f_j) * product + beta * C.
+ * dtype: GEMM_BF16 (T = 0), GEMM_F16 (T = 14) or GEMM_F8E4M3 (T = 7); other
+ * values return -14.  For data whose rows and columns span more magnitudes
+ * than the format holds (A = Dr A0 Dc with diagonal scalings over 2^+-20,
+ * say), where the plain FP16 and FP8 paths overflow or flush to zero.  The
+ * quantised operands live in a second per-stream workspace of about
+ * (m*k + k*n)*bytes + 4*(m + n) bytes (+ 4*m*n when beta != 0); if it
+ * cannot grow (allocation failure, or during a graph capture) the call
+ * returns GEMM_E_WORKSPACE.  Asynchronous on the current stream like gemm().
+ */
+int gemm_scaled(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha,
+                const void *A, int64_t lda, const void *B, int64_t ldb, double beta, void *C,
+                int64_t ldc, int dtype);
+
 /* One problem of a grouped call; the fields mean what gemm()'s arguments do. */
 typedef struct {
     char transA, transB;

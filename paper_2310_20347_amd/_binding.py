@@ -68,6 +68,8 @@ def lib():
         pass
     L = ctypes.CDLL(path)
     L.gemm.argtypes = [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64, _INT]
+    L.gemm_scaled.argtypes = [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64, _INT]
+    L.gemm_scaled.restype = _INT
     L.gemm.restype = _INT
     L.gemm_grouped.argtypes = [_I64, ctypes.POINTER(_Problem), _INT]
     L.gemm_grouped.restype = _INT
@@ -159,6 +161,17 @@ def gemm(transA: str, transB: str, m: int, n: int, k: int, alpha: float, A, lda:
     rc = lib().gemm(_tc(transA), _tc(transB), m, n, k, float(alpha), _ptr(A), lda, _ptr(B),
                     ldb, float(beta), _ptr(C), ldc, int(dtype))
     return _check(rc, "gemm") if check else rc
+
+
+def gemm_scaled(transA: str, transB: str, m: int, n: int, k: int, alpha: float, A, lda: int, B,
+                ldb: int, beta: float, C, ldc: int, dtype: int, stream: Any = None,
+                check: bool = True) -> int:
+    """Power-of-two scaled low-precision GEMM on FP32 A, B, C (dtype: the
+    format the product runs in: GEMM_BF16, GEMM_F16 or GEMM_F8E4M3)."""
+    set_stream(stream)
+    rc = lib().gemm_scaled(_tc(transA), _tc(transB), m, n, k, float(alpha), _ptr(A), lda,
+                           _ptr(B), ldb, float(beta), _ptr(C), ldc, int(dtype))
+    return _check(rc, "gemm_scaled") if check else rc
 
 
 @dataclass

@@ -395,10 +395,10 @@ void select_config(int kclass, int trans, int64_t m, int64_t n, int64_t k, int c
 }
 
 // Grow-only workspace of stream s on device d (NULL when it cannot be had).
-void *stream_workspace(DevState *d, hipStream_t s, size_t bytes)
+void *stream_workspace(DevState *d, hipStream_t s, size_t bytes, int slot)
 {
     std::lock_guard<std::mutex> g(d->ws_mu);
-    std::pair<void *, size_t> &w = d->ws[s];
+    std::pair<void *, size_t> &w = d->ws[{s, slot}];
     if (w.second >= bytes) return w.first;
     // never allocate, free or synchronise inside a graph capture: the caller
     // then runs a configuration that needs no workspace

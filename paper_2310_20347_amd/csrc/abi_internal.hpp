@@ -26,7 +26,7 @@ struct DevState {
     // packed split operands: one grow-only workspace per stream (work on one
     // stream is ordered, so its GEMMs can share it)
     std::mutex ws_mu;
-    std::map<hipStream_t, std::pair<void *, size_t>> ws;
+    std::map<std::pair<hipStream_t, int>, std::pair<void *, size_t>> ws;   // (stream, slot)
 };
 
 // Internal status of launch_gemm: a packed configuration could not get its
@@ -93,7 +93,9 @@ int64_t packed_k(int64_t k, int terms);
 int launch_split_pack(const float *X, int64_t ld, bool kmode, int64_t rows, int64_t k, int terms,
                       bool a_side, unsigned short *out, hipStream_t s);
 const void *split_pack_entry();
-void *stream_workspace(DevState *d, hipStream_t s, size_t bytes);
+// slot 0: the kernels' own workspace (packed split, split-K); slot 1: the
+// scaled path's quantised operands, which outlive the GEMM it calls
+void *stream_workspace(DevState *d, hipStream_t s, size_t bytes, int slot = 0);
 void free_workspaces(DevState *d);
 
 }  // namespace mg

@@ -1,0 +1,247 @@
+// Power-of-two scaled low-precision GEMM on FP32 operands (gemm_scaled).
+//
+// A narrow format (bfloat16, binary16, FP8 E4M3FN) covers a range of
+// magnitudes that badly scaled FP32 data overflows or underflows.  Each row
+// i of op(A) and each column j of op(B) is scaled by a power of two,
+// 2^-e_i and 2^-f_j, chosen to place its largest magnitude M in [2^T,
+// 2^(T+1)) (e = floor(log2 M) - T; T = 14 for binary16, 7 for E4M3, 0 for
+// bfloat16), and rounded to the format (nearest, ties to even; E4M3
+// saturates at 448).  The scalings are exact, so
+//     C = alpha * 2^(e_i + f_j) * sum_p qa(i,p) qb(p,j) + beta * C
+// with the product formed by the library's GEMM of that format (FP32
+// accumulation).  Rows or columns that are all zero or hold a non-finite
+// value are not scaled (e = 0).
+//
+// Passes: exponents of op(A) rows and op(B) columns; quantisation into the
+// stream's second workspace (operands kept in their stored layout, leading
+// dimensions rounded to 16 bytes so the GEMM takes its vectorised path); the
+// GEMM (into C when beta = 0, else into the workspace); the scaling epilogue.
+#include <hip/hip_runtime.h>
+
+#include "abi_internal.hpp"
+#include "mgemm.h"
+
+namespace mg {
+namespace {
+
+constexpr int kT_BF16 = 0, kT_F16 = 14, kT_E4M3 = 7;
+
+__device__ __forceinline__ int exponent_of_max(float mx, bool finite, int T)
+{
+    if (!finite || mx == 0.0f) return 0;
+    int ex;
+    (void)frexpf(mx, &ex);   // mx = f * 2^ex, f in [0.5, 1)
+    return (ex - 1) - T;
+}
+
+// Exponents of R vectors of length K: element p of vector r at X[r*ld + p]
+// (CONTIG: one workgroup per vector) or X[p*ld + r] (one thread per vector,
+// neighbouring threads on neighbouring addresses).
+template <bool CONTIG>
+__global__ void __launch_bounds__(256) vec_exponents(const float *X, int64_t ld, int R, int K, int T,
+                                                     int *e)
+{
+    if constexpr (CONTIG) {
+        __shared__ float s_max[256];
+        __shared__ int s_bad[256];
+        const int r = blockIdx.x;
+        float mx = 0.0f;
+        int bad = 0;
+        for (int p = threadIdx.x; p < K; p += 256) {
+            const float a = fabsf(X[(int64_t)r * ld + p]);
+            if (!(a <= 3.402823466e38f)) bad = 1;   // Inf or NaN
+            else mx = fmaxf(mx, a);
+        }
+        s_max[threadIdx.x] = mx;
+        s_bad[threadIdx.x] = bad;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) {
+                s_max[threadIdx.x] = fmaxf(s_max[threadIdx.x], s_max[threadIdx.x + w]);
+                s_bad[threadIdx.x] |= s_bad[threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) e[r] = exponent_of_max(s_max[0], !s_bad[0], T);
+    } else {
+        const int r = blockIdx.x * 256 + threadIdx.x;
+        if (r >= R) return;
+        float mx = 0.0f;
+        bool bad = false;
+        for (int p = 0; p < K; ++p) {
+            const float a = fabsf(X[(int64_t)p * ld + r]);
+            if (!(a <= 3.402823466e38f)) bad = true;
+            else mx = fmaxf(mx, a);
+        }
+        e[r] = exponent_of_max(mx, !bad, T);
+    }
+}
+
+// Round-to-nearest-even encoders on the FP32 bit pattern.
+__device__ __forceinline__ u32 rne_drop(u32 base, u32 rem, u32 half)
+{
+    return base + ((rem > half || (rem == half && (base & 1u))) ? 1u : 0u);
+}
+
+__device__ __forceinline__ unsigned short enc_f16(float y)
+{
+    const u32 u = __builtin_bit_cast(u32, y);
+    const u32 s = (u >> 16) & 0x8000u, a = u & 0x7FFFFFFFu;
+    if (a > 0x7F800000u) return (unsigned short)(s | 0x7E00u);
+    const u32 e = a >> 23;
+    if (e >= 113) {   // |y| >= 2^-14: binary16 normal range (or overflow)
+        const u32 q = rne_drop((a >> 13) - (112u << 10), a & 0x1FFFu, 0x1000u);
+        return (unsigned short)(s | (q >= 0x7C00u ? 0x7C00u : q));
+    }
+    if (e < 102) return (unsigned short)s;   // below half the smallest subnormal
+    const u32 m = (a & 0x7FFFFFu) | 0x800000u, sh = 126u - e;   // q = y * 2^24
+    return (unsigned short)(s | rne_drop(m >> sh, m & ((1u << sh) - 1u), 1u << (sh - 1u)));
+}
+
+__device__ __forceinline__ unsigned char enc_e4m3(float y)
+{
+    const u32 u = __builtin_bit_cast(u32, y);
+    const u32 s = (u >> 24) & 0x80u, a = u & 0x7FFFFFFFu;
+    if (a > 0x7F800000u) return (unsigned char)(s | 0x7Fu);
+    const u32 e = a >> 23;
+    if (e >= 121) {   // |y| >= 2^-6: normal range, saturating at 448 (code 0x7E)
+        const u32 q = e >= 136 ? 0x7Fu : rne_drop(((e - 120u) << 3) | ((a >> 20) & 7u), a & 0xFFFFFu, 0x80000u);
+        return (unsigned char)(s | (q > 0x7Eu ? 0x7Eu : q));
+    }
+    if (e < 117) return (unsigned char)s;   // below half of 2^-9
+    const u32 m = (a & 0x7FFFFFu) | 0x800000u, sh = 141u - e;   // q = y * 2^9
+    return (unsigned char)(s | rne_drop(m >> sh, m & ((1u << sh) - 1u), 1u << (sh - 1u)));
+}
+
+// Q = codes of the stored rows x cols matrix X scaled by 2^-e[index], the
+// index being the element's row (BY_ROW) or column.
+template <int FMT, bool BY_ROW>
+__global__ void __launch_bounds__(256) quantize(const float *X, int64_t ld, int rows, int cols,
+                                                const int *e, void *Q, int64_t ldq)
+{
+    const int64_t total = (int64_t)rows * cols;
+    for (int64_t t = blockIdx.x * 256ll + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+        const int r = (int)(t / cols), c = (int)(t - (int64_t)r * cols);
+        const float y = ldexpf(X[(int64_t)r * ld + c], -e[BY_ROW ? r : c]);
+        if constexpr (FMT == 0) ((unsigned short *)Q)[(int64_t)r * ldq + c] = (unsigned short)bf16_bits(y);
+        else if constexpr (FMT == 1) ((unsigned short *)Q)[(int64_t)r * ldq + c] = enc_f16(y);
+        else ((unsigned char *)Q)[(int64_t)r * ldq + c] = enc_e4m3(y);
+    }
+}
+
+// C = alpha * 2^(e_i + f_j) * P + beta * C (C not read when beta = 0; P may be C).
+__global__ void __launch_bounds__(256) scale_epilogue(const float *P, int64_t ldp, float *C,
+                                                      int64_t ldc, int m, int n, const int *e,
+                                                      const int *f, float alpha, float beta)
+{
+    const int64_t total = (int64_t)m * n;
+    for (int64_t t = blockIdx.x * 256ll + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+        const int i = (int)(t / n), j = (int)(t - (int64_t)i * n);
+        float v = alpha * ldexpf(P[(int64_t)i * ldp + j], e[i] + f[j]);
+        if (beta != 0.0f) v = fmaf(beta, C[(int64_t)i * ldc + j], v);
+        C[(int64_t)i * ldc + j] = v;
+    }
+}
+
+unsigned grid_for(int64_t total)
+{
+    int64_t b = (total + 255) / 256;
+    return (unsigned)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
+}
+
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+bool is_trans(char t) { return t == 'T' || t == 't' || t == 'C' || t == 'c'; }
+
+template <int FMT>
+void launch_quantize(bool by_row, const float *X, int64_t ld, int rows, int cols, const int *e, void *Q,
+                     int64_t ldq, hipStream_t s)
+{
+    const unsigned g = grid_for((int64_t)rows * cols);
+    if (by_row)
+        hipLaunchKernelGGL((quantize<FMT, true>), dim3(g), dim3(256), 0, s, X, ld, rows, cols, e, Q, ldq);
+    else
+        hipLaunchKernelGGL((quantize<FMT, false>), dim3(g), dim3(256), 0, s, X, ld, rows, cols, e, Q, ldq);
+}
+
+// Exponents of the R op-vectors of length K stored in X (contiguous or not).
+void launch_exponents(bool contig, const float *X, int64_t ld, int R, int K, int T, int *e, hipStream_t s)
+{
+    if (contig)
+        hipLaunchKernelGGL(vec_exponents<true>, dim3((unsigned)R), dim3(256), 0, s, X, ld, R, K, T, e);
+    else
+        hipLaunchKernelGGL(vec_exponents<false>, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, X, ld,
+                           R, K, T, e);
+}
+
+}  // namespace
+}  // namespace mg
+
+using namespace mg;
+
+extern "C" int gemm_scaled(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha,
+                           const void *A, int64_t lda, const void *B, int64_t ldb, double beta, void *C,
+                           int64_t ldc, int dtype)
+{
+    if (dtype != GEMM_BF16 && dtype != GEMM_F16 && dtype != GEMM_F8E4M3) return -14;
+    // FP32 operands and C: the FP32 rules of gemm()
+    const int v = validate(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, GEMM_F32);
+    if (v != 0) return v;
+    if (m == 0 || n == 0) return GEMM_OK;
+    if (alpha == 0.0 || k == 0) return gemm(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, GEMM_F32);
+    if (m > 0x7FFFFFFF || n > 0x7FFFFFFF || k > 0x7FFFFFFF) return GEMM_E_UNSUPPORTED;
+    ensure_registered();
+    DevState *d = nullptr;
+    int rc = device_state(&d);
+    if (rc != GEMM_OK) return rc;
+    hipStream_t s = t_tls.stream;
+    const bool ta = is_trans(transA), tb = is_trans(transB);
+    const int fmt = dtype == GEMM_BF16 ? 0 : (dtype == GEMM_F16 ? 1 : 2);
+    const int T = fmt == 0 ? kT_BF16 : (fmt == 1 ? kT_F16 : kT_E4M3);
+    const int es = fmt == 2 ? 1 : 2;
+    // stored shapes: A is m x k ('N') or k x m ('T'); B is k x n ('N') or n x k ('T')
+    const int64_t ar = ta ? k : m, ac = ta ? m : k, br = tb ? n : k, bc = tb ? k : n;
+    const int64_t ldqa = round_up(ac, 16 / es), ldqb = round_up(bc, 16 / es);
+    const int64_t e_bytes = round_up(m * 4, 256), f_bytes = round_up(n * 4, 256);
+    const int64_t qa_bytes = round_up(ar * ldqa * es, 256), qb_bytes = round_up(br * ldqb * es, 256);
+    const int64_t p_bytes = beta != 0.0 ? m * n * 4 : 0;
+    char *ws = (char *)stream_workspace(d, s, (size_t)(e_bytes + f_bytes + qa_bytes + qb_bytes + p_bytes), 1);
+    if (!ws) return GEMM_E_WORKSPACE;
+    int *e = (int *)ws, *f = (int *)(ws + e_bytes);
+    char *qa = ws + e_bytes + f_bytes, *qb = qa + qa_bytes;
+    float *P = p_bytes ? (float *)(qb + qb_bytes) : (float *)C;
+    const int64_t ldp = p_bytes ? n : ldc;
+    // op(A) row i: stored row i ('N', contiguous) or stored column i ('T');
+    // op(B) column j: stored column j ('N') or stored row j ('T', contiguous)
+    launch_exponents(!ta, (const float *)A, lda, (int)m, (int)k, T, e, s);
+    launch_exponents(tb, (const float *)B, ldb, (int)n, (int)k, T, f, s);
+    switch (fmt) {
+    case 0:
+        launch_quantize<0>(!ta, (const float *)A, lda, (int)ar, (int)ac, e, qa, ldqa, s);
+        launch_quantize<0>(tb, (const float *)B, ldb, (int)br, (int)bc, f, qb, ldqb, s);
+        break;
+    case 1:
+        launch_quantize<1>(!ta, (const float *)A, lda, (int)ar, (int)ac, e, qa, ldqa, s);
+        launch_quantize<1>(tb, (const float *)B, ldb, (int)br, (int)bc, f, qb, ldqb, s);
+        break;
+    default:
+        launch_quantize<2>(!ta, (const float *)A, lda, (int)ar, (int)ac, e, qa, ldqa, s);
+        launch_quantize<2>(tb, (const float *)B, ldb, (int)br, (int)bc, f, qb, ldqb, s);
+        break;
+    }
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) {
+        t_tls.hip_err = (int)err;
+        return GEMM_E_HIP;
+    }
+    rc = gemm(transA, transB, m, n, k, 1.0, qa, ldqa, qb, ldqb, 0.0, P, ldp, dtype);
+    if (rc != GEMM_OK) return rc;
+    hipLaunchKernelGGL(scale_epilogue, dim3(grid_for(m * n)), dim3(256), 0, s, (const float *)P, ldp,
+                       (float *)C, ldc, (int)m, (int)n, e, f, (float)alpha, (float)beta);
+    err = hipGetLastError();
+    if (err != hipSuccess) {
+        t_tls.hip_err = (int)err;
+        return GEMM_E_HIP;
+    }
+    return GEMM_OK;
+}

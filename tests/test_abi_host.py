@@ -127,3 +127,13 @@ def test_grouped_validation_before_device():
     assert mg.lib().gemm_grouped(3, arr, 42) == -3
     assert mg.lib().gemm_grouped(0, None, mg.GEMM_F32) == 0
     assert mg.gemm_grouped_capacity() >= 512
+
+
+def test_gemm_scaled_validates_before_touching_the_device():
+    # only the narrow formats; FP32 argument rules; quick return for m == 0
+    L = mg.lib()
+    n_, p_ = b"N", 0x1000
+    assert L.gemm_scaled(n_, n_, 4, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, mg.GEMM_F32) == -14
+    assert L.gemm_scaled(n_, n_, 4, 4, 4, 1.0, p_, 2, p_, 4, 0.0, p_, 4, mg.GEMM_F16) == -8
+    assert L.gemm_scaled(b"X", n_, 4, 4, 4, 1.0, p_, 4, p_, 4, 0.0, p_, 4, mg.GEMM_F8E4M3) == -1
+    assert L.gemm_scaled(n_, n_, 0, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, mg.GEMM_BF16) == 0

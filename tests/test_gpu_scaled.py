@@ -1,0 +1,132 @@
+"""GPU parity of the power-of-two scaled low-precision GEMM (gemm_scaled)
+against the oracle's definition of the same scaling and rounding.
+
+* Encoders: with k = 2 and B picking one column of A, C is exactly the
+  dequantised scaled code of each A value, so every code is compared bit for
+  bit (and the same with the roles of A and B swapped).
+* Products: within the FP32-accumulation bound of the oracle on the same
+  codes (FP8 with its MFMA allowance), every layout, ragged sizes, beta 0
+  and not.
+* Source error on badly scaled inputs, where the plain FP16 and FP8 paths
+  overflow: within the format's bound (binary16 / bfloat16 8e-3, E4M3 6.25e-2).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2310_20347_amd as mg
+from paper_2310_20347_amd import inputs
+
+from gemm_cases import QUANT_TOL, stored, to_device
+
+pytestmark = pytest.mark.gpu
+
+FMTS = [(mg.GEMM_BF16, "bf16", 8e-3), (mg.GEMM_F16, "f16", 8e-3), (mg.GEMM_F8E4M3, "e4m3", 6.25e-2)]
+TRANS = [("N", "N"), ("N", "T"), ("T", "N"), ("T", "T")]
+
+
+def run_scaled(dtype, ta, tb, a32, b32, alpha, beta, c0, pad=0):
+    import torch
+    m, k = a32.shape
+    n = b32.shape[1]
+    lda = (m if ta == "T" else k) + pad
+    ldb = (k if tb == "T" else n) + pad
+    ldc = n + pad
+    As, Bs, Cs = stored(a32, ta, lda), stored(b32, tb, ldb), stored(c0, "N", ldc)
+    dC = to_device(Cs.reshape(-1).copy())
+    mg.gemm_scaled(ta, tb, m, n, k, alpha, to_device(As), lda, to_device(Bs), ldb, beta, dC,
+                   ldc, dtype)
+    torch.cuda.synchronize()
+    C = dC.cpu().numpy().reshape(m, ldc)[:, :n]
+    ref = oracle.gemm_scaled(ta, tb, m, n, k, alpha, As, lda, Bs, ldb,
+                             {mg.GEMM_BF16: "bf16", mg.GEMM_F16: "f16", mg.GEMM_F8E4M3: "e4m3"}[dtype],
+                             beta, Cs, ldc)[0]
+    return C, ref
+
+
+def _fp8_allowance(fmt, k):
+    # the FP8 MFMA sums the 128 products of one instruction to about 12 bits
+    return 1.07 * 2.0 ** -11 * ((k + 127) // 128) / k if fmt == "e4m3" else 0.0
+
+
+@pytest.mark.parametrize("dtype,fmt,_tol", FMTS, ids=[f[1] for f in FMTS])
+def test_scaled_codes_bit_exact(dtype, fmt, _tol):
+    # A[:, 0] sets each row's exponent, A[:, 1] sweeps values (ties, subnormal
+    # codes, saturation below the row maximum); B = [[0], [1]] picks A[:, 1]
+    rng = np.random.default_rng(31)
+    rows = 4096
+    top = np.exp2(rng.integers(-30, 30, rows)).astype(np.float32)
+    frac = rng.uniform(-1, 1, rows) * np.exp2(-rng.integers(0, 30, rows).astype(np.float64))
+    a = np.stack([top, (top * frac).astype(np.float32)], axis=1)
+    b = np.array([[0.0], [1.0]], np.float32)
+    for ta in ("N", "T"):
+        C, ref = run_scaled(dtype, ta, "N", a, b, 1.0, 0.0, np.zeros((rows, 1), np.float32))
+        assert np.array_equal(C[:, 0].astype(np.float64), ref[:, 0]), f"{fmt} {ta}"
+    # the same with the roles of A and B swapped: C = [0 1] * B picks B's row 1
+    bt = a.T.copy()
+    a2 = np.array([[0.0, 1.0]], np.float32)
+    for tb in ("N", "T"):
+        C, ref = run_scaled(dtype, "N", tb, a2, bt, 1.0, 0.0, np.zeros((1, rows), np.float32))
+        assert np.array_equal(C[0].astype(np.float64), ref[0]), f"{fmt} B {tb}"
+
+
+@pytest.mark.parametrize("dtype,fmt,tol", FMTS, ids=[f[1] for f in FMTS])
+@pytest.mark.parametrize("ta,tb", TRANS)
+@pytest.mark.parametrize("dist", ["uniform", "badly_scaled"])
+def test_scaled_gemm_parity(dtype, fmt, tol, ta, tb, dist):
+    for (m, n, k), beta, seed in (((257, 190, 203), 0.0, 1), ((64, 129, 1000), -0.5, 2)):
+        if dist == "uniform":
+            a = inputs.uniform((m, k), 40 + seed)
+            b = inputs.uniform((k, n), 50 + seed)
+        else:
+            a = inputs.badly_scaled(m, k, 40 + seed)
+            b = inputs.badly_scaled(k, n, 50 + seed)
+        c0 = inputs.uniform((m, n), 60 + seed)
+        print(f"{fmt} {ta}{tb} {dist} {m}x{n}x{k} beta {beta}", flush=True)
+        C, ref = run_scaled(dtype, ta, tb, a, b, 1.25, beta, c0, pad=3)
+        assert np.all(np.isfinite(C))
+        ma, mb = float(np.abs(a).max()), float(np.abs(b).max())
+        err_q = oracle.normalized_error(C, ref, k * 1.25, ma, mb)
+        assert err_q <= QUANT_TOL + _fp8_allowance(fmt, k), f"quantised-input error {err_q:.3g}"
+        src = oracle.gemm_f64(ta, tb, m, n, k, 1.25, stored(a, ta, a.shape[1] if ta == "N" else m),
+                              k if ta == "N" else m, stored(b, tb, n if tb == "N" else k),
+                              n if tb == "N" else k, beta, c0, n)
+        err_s = oracle.normalized_error(C, src, k * 1.25, ma, mb)
+        assert err_s <= tol, f"source error {err_s:.3g} > {tol}"
+
+
+def test_scaled_special_cases():
+    import torch
+    m, n, k = 33, 21, 40
+    a = inputs.uniform((m, k), 70)
+    b = inputs.uniform((k, n), 71)
+    # zero rows and columns stay exact zeros (exponent 0)
+    a[5] = 0.0
+    b[:, 7] = 0.0
+    C, ref = run_scaled(mg.GEMM_F16, "N", "N", a, b, 1.0, 0.0, np.zeros((m, n), np.float32))
+    assert np.all(C[5] == 0) and np.all(C[:, 7] == 0)
+    assert oracle.normalized_error(C, ref, k, 1.0, 1.0) <= QUANT_TOL
+    # k == 0 and alpha == 0: C = beta * C
+    C0 = torch.arange(m * n, dtype=torch.float32, device="cuda").reshape(m, n)
+    C1 = C0.clone()
+    mg.gemm_scaled("N", "N", m, n, 0, 1.0, None, 1, None, n, 2.0, C1, n, mg.GEMM_F8E4M3)
+    C2 = C0.clone()
+    dA = to_device(a)
+    mg.gemm_scaled("N", "N", m, n, k, 0.0, dA, k, dA, n, 3.0, C2, n, mg.GEMM_BF16)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, 2 * C0) and torch.equal(C2, 3 * C0)
+
+
+def test_unscaled_fp16_overflows_where_scaled_does_not():
+    # the reason for the scaled path: badly scaled data overflow binary16
+    m, n, k = 96, 80, 128
+    a = inputs.badly_scaled(m, k, 80)
+    b = inputs.badly_scaled(k, n, 81)
+    import torch
+    dC = torch.zeros((m, n), dtype=torch.float32, device="cuda")
+    mg.gemm("N", "N", m, n, k, 1.0, to_device(inputs.to_f16_bits(a)), k,
+            to_device(inputs.to_f16_bits(b)), n, 0.0, dC, n, mg.GEMM_F16)
+    torch.cuda.synchronize()
+    assert not np.all(np.isfinite(dC.cpu().numpy()))
+    C, _ = run_scaled(mg.GEMM_F16, "N", "N", a, b, 1.0, 0.0, np.zeros((m, n), np.float32))
+    assert np.all(np.isfinite(C))
