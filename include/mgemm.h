@@ -259,6 +259,22 @@ int gemm_tune(int dtype, int64_t count, const int64_t *shapes, int reps,
               const char *out_path);
 
 /*
+ * gemm_tune restricted to the model_keep configurations the analytical model
+ * ranks first for each shape (0: all of them, which is gemm_tune); -6 when
+ * model_keep < 0.  The model (gemm_model_us) predicts occupancy from LDS and
+ * register use, the rounds of tiles over the compute units, and a tile's
+ * time as the largest of its MFMA, L2->LDS and LDS-read times plus the load
+ * latency its stage ring leaves exposed.  It also picks the configuration
+ * for sizes the tuning table does not cover.
+ */
+int gemm_tune_pruned(int dtype, int64_t count, const int64_t *shapes, int reps,
+                     const char *out_path, int model_keep);
+
+/* Modelled time in microseconds of configuration `id` of `dtype` on an
+ * m x n x k problem over `cus` compute units; -1 on invalid arguments. */
+double gemm_model_us(int dtype, int id, int64_t m, int64_t n, int64_t k, int cus);
+
+/*
  * Fraction of a memory of `capacity_bytes` occupied by a rows x cols panel of
  * `elem_bytes`-byte values: the occupancy measure of the paper's analytical
  * cache model (section 8.4, Table 2: the L1 share of the micro-panel Br =

@@ -11,6 +11,7 @@ from ._binding import (  # noqa: F401
     GEMM_F64, GEMM_F8E4M3, GEMM_I8, GEMM_NUM_DTYPES, DTYPE_NAMES, MGemmError, Problem, config_info, config_supports,
     force_config,
     gemm, gemm_scaled, gemm_grouped, gemm_grouped_capacity, gemm_init, gemm_shutdown, gemm_tune,
-    GroupedSlot, PackedProblems, last_config, lib, lib_path, num_configs, panel_occupancy,
+    GroupedSlot, PackedProblems, last_config, lib, lib_path, model_us, num_configs,
+    panel_occupancy,
     set_stream, strerror,
 )

@@ -106,6 +106,10 @@ def lib():
     L.gemm_last_config.argtypes = [ctypes.POINTER(_I64)]
     L.gemm_last_config.restype = _INT
     L.gemm_tune.argtypes = [_INT, _I64, ctypes.POINTER(_I64), _INT, ctypes.c_char_p]
+    L.gemm_tune_pruned.argtypes = [_INT, _I64, ctypes.POINTER(_I64), _INT, ctypes.c_char_p, _INT]
+    L.gemm_tune_pruned.restype = _INT
+    L.gemm_model_us.argtypes = [_INT, _INT, _I64, _I64, _I64, _INT]
+    L.gemm_model_us.restype = ctypes.c_double
     L.gemm_tune.restype = _INT
     L.gemm_panel_occupancy.argtypes = [_I64, _I64, _I64, _I64]
     L.gemm_panel_occupancy.restype = _D
@@ -290,10 +294,18 @@ def last_config() -> dict:
 
 
 def gemm_tune(dtype: int, shapes: Sequence[Sequence[int]], reps: int = 10,
-              out_path: Optional[str] = None) -> None:
+              out_path: Optional[str] = None, model_keep: int = 0) -> None:
+    """Times the configurations on each shape (only the model's first
+    model_keep when > 0) and stores the fastest per size bucket."""
     flat = (_I64 * max(1, 3 * len(shapes)))(*[int(v) for s in shapes for v in s])
     p = out_path.encode() if out_path else None
-    _check(lib().gemm_tune(int(dtype), len(shapes), flat, int(reps), p), "gemm_tune")
+    _check(lib().gemm_tune_pruned(int(dtype), len(shapes), flat, int(reps), p, int(model_keep)),
+           "gemm_tune")
+
+
+def model_us(dtype: int, cfg: int, m: int, n: int, k: int, cus: int = 256) -> float:
+    """The analytical model's time (microseconds) of configuration cfg."""
+    return float(lib().gemm_model_us(int(dtype), int(cfg), m, n, k, int(cus)))
 
 
 def panel_occupancy(rows: int, cols: int, elem_bytes: int, capacity_bytes: int) -> float:

@@ -348,23 +348,11 @@ static void ensure_table()
 
 // Default choice without a table entry: the tile that minimises a crude
 // cost = waves of workgroups x per-tile work (mc*nc) + panel traffic (mc+nc).
-static void heuristic(int kclass, int64_t m, int64_t n, int cus, int &id, int &order, int &group)
+// No tuned entry: the configuration the analytical model ranks first.
+static void heuristic(int kclass, int trans, int64_t m, int64_t n, int64_t k, int cus, int &id,
+                      int &order, int &group)
 {
-    const std::vector<int> &ids = g_by_class[kclass];
-    double best = 1e300;
-    id = 0;
-    for (size_t i = 0; i < ids.size(); ++i) {
-        const KernelCfg &c = g_cfgs[ids[i]];
-        if (c.kind != 0) continue;
-        const double tiles = double((m + c.mc - 1) / c.mc) * double((n + c.nc - 1) / c.nc);
-        const double slots = double(cus) * std::max(1, (160 * 1024) / std::max(c.lds, 1));
-        const double waves = std::ceil(tiles / std::min(slots, double(cus) * 2));
-        const double cost = waves * (double(c.mc) * c.nc + 48.0 * (c.mc + c.nc));
-        if (cost < best * 0.999) {
-            best = cost;
-            id = (int)i;
-        }
-    }
+    id = model_best(kclass, trans, true, m, n, k, cus);
     order = 0;
     group = 8;
 }
@@ -391,7 +379,7 @@ void select_config(int kclass, int trans, int64_t m, int64_t n, int64_t k, int c
             }
         }
     }
-    heuristic(kclass, m, n, cus, id, order, group);
+    heuristic(kclass, trans, m, n, k, cus, id, order, group);
 }
 
 // Grow-only workspace of stream s on device d (NULL when it cannot be had).

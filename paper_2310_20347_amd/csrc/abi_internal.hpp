@@ -96,6 +96,12 @@ const void *split_pack_entry();
 // slot 0: the kernels' own workspace (packed split, split-K); slot 1: the
 // scaled path's quantised operands, which outlive the GEMM it calls
 void *stream_workspace(DevState *d, hipStream_t s, size_t bytes, int slot = 0);
+
+// Analytical model (model.cpp): cycles / microseconds of configuration c on
+// an m x n x k problem, and the class's configuration it ranks first.
+double model_cycles(const KernelCfg &c, int kclass, int64_t m, int64_t n, int64_t k, int cus);
+double model_us(const KernelCfg &c, int kclass, int64_t m, int64_t n, int64_t k, int cus);
+int model_best(int kclass, int trans, bool vec, int64_t m, int64_t n, int64_t k, int cus);
 void free_workspaces(DevState *d);
 
 }  // namespace mg

@@ -44,13 +44,14 @@ extern "C" double gemm_panel_occupancy(int64_t rows, int64_t cols, int64_t elem_
     return double(rows) * double(cols) * double(elem_bytes) / double(capacity_bytes);
 }
 
-extern "C" int gemm_tune(int dtype, int64_t count, const int64_t *shapes, int reps,
-                         const char *out_path)
+extern "C" int gemm_tune_pruned(int dtype, int64_t count, const int64_t *shapes, int reps,
+                                const char *out_path, int model_keep)
 {
     if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -1;
     if (count < 0) return -2;
     if (count > 0 && !shapes) return -3;
     if (reps < 1) return -4;
+    if (model_keep < 0) return -6;
     ensure_registered();
     DevState *d = nullptr;
     int rc = device_state(&d);
@@ -103,9 +104,19 @@ extern "C" int gemm_tune(int dtype, int64_t count, const int64_t *shapes, int re
         };
         std::vector<Cand> cands;
         const std::vector<int> &ids = g_by_class[kclass];
+        // model pruning: only the model_keep configurations it ranks first
+        std::vector<bool> keep(ids.size(), true);
+        if (model_keep > 0 && (size_t)model_keep < ids.size()) {
+            std::vector<std::pair<double, size_t>> r;
+            for (size_t id = 0; id < ids.size(); ++id)
+                r.push_back({model_cycles(g_cfgs[ids[id]], kclass, m, n, k, d->cus), id});
+            std::sort(r.begin(), r.end());
+            keep.assign(ids.size(), false);
+            for (int i = 0; i < model_keep; ++i) keep[r[(size_t)i].second] = true;
+        }
         for (size_t id = 0; id < ids.size(); ++id) {
             const KernelCfg &c = g_cfgs[ids[id]];
-            if (!c.func[0][1]) continue;
+            if (!c.func[0][1] || !keep[id]) continue;
             hipFuncAttributes attr;
             if (hipFuncGetAttributes(&attr, c.func[0][1]) == hipSuccess && attr.localSizeBytes > 0)
                 continue;   // spills: rejected
@@ -197,4 +208,9 @@ extern "C" int gemm_tune(int dtype, int64_t count, const int64_t *shapes, int re
     rebuild_lut();
     if (out_path && *out_path) return save_table(out_path);
     return GEMM_OK;
+}
+
+extern "C" int gemm_tune(int dtype, int64_t count, const int64_t *shapes, int reps, const char *out_path)
+{
+    return gemm_tune_pruned(dtype, count, shapes, reps, out_path, 0);
 }

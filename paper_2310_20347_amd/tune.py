@@ -6,7 +6,8 @@ raster order, raster group) on representative shapes of each size bucket
 which the library loads by default.  Shapes: a coarse log grid of m, n, k
 plus the benchmark workloads' own shapes.
 
-    python -m paper_2310_20347_amd.tune [--quick] [--out PATH]
+    python -m paper_2310_20347_amd.tune [--quick] [--out PATH] [--model-keep N]
+    python -m paper_2310_20347_amd.tune --model-check [--dtypes 0,1,2]
 """
 import argparse
 import itertools
@@ -46,17 +47,87 @@ def main():
     p.add_argument("--reps", type=int, default=5)
     p.add_argument("--out", default=os.path.join(HERE, "mgemm_tune.json"))
     p.add_argument("--dtypes", default="0,1,2,3,4,5,7,8")
+    p.add_argument("--model-keep", type=int, default=0,
+                   help="time only the analytical model's first N configurations per shape")
+    p.add_argument("--model-check", action="store_true",
+                   help="measure the analytical model instead of tuning: time every "
+                        "configuration on a sample of shapes and report how much slower the "
+                        "model's first choice (and the shipped table's) is than the fastest")
     a = p.parse_args()
     import torch
     torch.cuda.set_device(0)
     mg.gemm_init(None)
+    if a.model_check:
+        return model_check([int(x) for x in a.dtypes.split(",")], a.reps, torch)
     for dt in [int(x) for x in a.dtypes.split(",")]:
         shapes = shapes_for(dt, a.quick)
         t0 = time.time()
-        mg.gemm_tune(dt, shapes, reps=a.reps, out_path=a.out)
+        mg.gemm_tune(dt, shapes, reps=a.reps, out_path=a.out, model_keep=a.model_keep)
         print(f"tuned {mg.DTYPE_NAMES[dt]}: {len(shapes)} shapes in {time.time() - t0:.1f} s",
               flush=True)
     print(f"wrote {a.out}")
+
+
+def model_check(dtypes, reps, torch):
+    import numpy as np
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    rng = np.random.default_rng(5)
+    grid = (64, 256, 1024, 4096)
+    cube = list(itertools.product(grid, grid, grid))
+    shapes = [cube[i] for i in rng.choice(len(cube), 20, replace=False)]
+    shapes += [(8192, 8192, 8192), (196, 1024, 4608), (50176, 64, 576)]
+
+    def operand(dt, r, c):
+        if dt in (mg.GEMM_BF16, mg.GEMM_F16):
+            return (torch.rand((r, c), device="cuda") * 2 - 1).to(torch.bfloat16).view(torch.int16)
+        if dt in (mg.GEMM_F8E4M3, mg.GEMM_I8):
+            return torch.randint(-8, 8, (r, c), device="cuda", dtype=torch.int8)
+        if dt == mg.GEMM_F64:
+            return torch.rand((r, c), device="cuda", dtype=torch.float64) * 2 - 1
+        return torch.rand((r, c), device="cuda") * 2 - 1
+
+    def timed(f):
+        f()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            f()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    for dt in dtypes:
+        model_loss, table_loss = [], []
+        for (m, n, k) in shapes:
+            A, B = operand(dt, m, k), operand(dt, k, n)
+            ct = {mg.GEMM_I8: torch.int32, mg.GEMM_F64: torch.float64}.get(dt, torch.float32)
+            C = torch.empty((m, n), device="cuda", dtype=ct)
+            fam = mg.GEMM_F32_BF16X6 if (dt == mg.GEMM_F32_BF16X3 and k < 64) else dt
+            times, model = {}, {}
+            try:
+                for cfg in range(mg.num_configs(fam)):
+                    if not mg.config_supports(fam, cfg, "N", "N"):
+                        continue
+                    mg.force_config(dt, cfg, 0)
+                    times[cfg] = timed(lambda: mg.gemm("N", "N", m, n, k, 1, A, k, B, n, 0, C, n, dt))
+                    model[cfg] = mg.model_us(fam, cfg, m, n, k, cus)
+            finally:
+                mg.force_config(dt, -1, 0)
+            table = timed(lambda: mg.gemm("N", "N", m, n, k, 1, A, k, B, n, 0, C, n, dt))
+            best = min(times.values())
+            model_loss.append(times[min(model, key=model.get)] / best)
+            table_loss.append(table / best)
+            del A, B, C
+        ml, tl = np.array(model_loss), np.array(table_loss)
+        print(f"{mg.DTYPE_NAMES[dt]:>7}: model's choice / fastest: mean {ml.mean():.3f}, median "
+              f"{np.median(ml):.3f}, max {ml.max():.2f}, within 10% on {np.mean(ml <= 1.1):.0%} "
+              f"of {len(ml)} shapes | shipped table: mean {tl.mean():.3f}, max {tl.max():.2f}",
+              flush=True)
+    return 0
 
 
 if __name__ == "__main__":

@@ -137,3 +137,20 @@ def test_gemm_scaled_validates_before_touching_the_device():
     assert L.gemm_scaled(n_, n_, 4, 4, 4, 1.0, p_, 2, p_, 4, 0.0, p_, 4, mg.GEMM_F16) == -8
     assert L.gemm_scaled(b"X", n_, 4, 4, 4, 1.0, p_, 4, p_, 4, 0.0, p_, 4, mg.GEMM_F8E4M3) == -1
     assert L.gemm_scaled(n_, n_, 0, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, mg.GEMM_BF16) == 0
+
+
+def test_analytical_model_structure():
+    """The analytical model's rules, on the CPU (no device: register counts
+    estimated): invalid arguments; time grows with k; one round of tiles
+    costs the same whatever the tile count; split-K first for a tall-k
+    problem whose output fills a quarter of the compute units."""
+    assert mg.model_us(mg.GEMM_F32, 0, 0, 64, 64) == -1.0
+    assert mg.model_us(mg.GEMM_F32, 999, 64, 64, 64) == -1.0
+    t = [mg.model_us(mg.GEMM_F32, 0, 512, 512, k) for k in (256, 1024, 4096)]
+    assert 0 < t[0] < t[1] < t[2]
+    one = mg.model_us(mg.GEMM_BF16, 0, 64, 64, 1024)
+    assert mg.model_us(mg.GEMM_BF16, 0, 640, 640, 1024) == pytest.approx(one, rel=1e-9)
+    assert mg.model_us(mg.GEMM_BF16, 0, 64 * 64, 64 * 64, 1024) > 1.5 * one
+    ranked = sorted(range(mg.num_configs(mg.GEMM_F32)),
+                    key=lambda c: mg.model_us(mg.GEMM_F32, c, 196, 1024, 4608))
+    assert mg.config_info(mg.GEMM_F32, ranked[0])["kind"] == 6
