@@ -49,7 +49,9 @@ typedef struct {
     int max_active;            /* requests admitted at once (slots)                       */
     int64_t step_tile_budget;  /* max 128x128 output tiles issued per step                */
     int64_t request_tile_cap;  /* max tiles of one request per step                       */
-    int inflight_steps;        /* steps in flight per dtype stream, 1..4                  */
+    int inflight_steps;        /* steps in flight per dtype stream, 1..4 (1 keeps the     */
+                               /* latency lowest: arrivals join the next step instead of  */
+                               /* queueing behind a second launch on the stream)          */
     double watchdog_s;         /* a step unfinished after this long ends the run          */
     int64_t warmup_requests;   /* first requests (by arrival) left out of the statistics  */
 } serve_config;
