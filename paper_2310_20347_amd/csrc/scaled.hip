@@ -18,6 +18,8 @@
 // GEMM (into C when beta = 0, else into the workspace); the scaling epilogue.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "abi_internal.hpp"
 #include "mgemm.h"
 
@@ -34,47 +36,64 @@ __device__ __forceinline__ int exponent_of_max(float mx, bool finite, int T)
     return (ex - 1) - T;
 }
 
-// Exponents of R vectors of length K: element p of vector r at X[r*ld + p]
-// (CONTIG: one workgroup per vector) or X[p*ld + r] (one thread per vector,
-// neighbouring threads on neighbouring addresses).
-template <bool CONTIG>
-__global__ void __launch_bounds__(256) vec_exponents(const float *X, int64_t ld, int R, int K, int T,
-                                                     int *e)
+// Exponents of R vectors of length K, element p of vector r at X[r*ld + p]:
+// one workgroup per vector.
+__global__ void __launch_bounds__(256) row_exponents(const float *X, int64_t ld, int K, int T, int *e)
 {
-    if constexpr (CONTIG) {
-        __shared__ float s_max[256];
-        __shared__ int s_bad[256];
-        const int r = blockIdx.x;
-        float mx = 0.0f;
-        int bad = 0;
-        for (int p = threadIdx.x; p < K; p += 256) {
-            const float a = fabsf(X[(int64_t)r * ld + p]);
-            if (!(a <= 3.402823466e38f)) bad = 1;   // Inf or NaN
-            else mx = fmaxf(mx, a);
-        }
-        s_max[threadIdx.x] = mx;
-        s_bad[threadIdx.x] = bad;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) {
-                s_max[threadIdx.x] = fmaxf(s_max[threadIdx.x], s_max[threadIdx.x + w]);
-                s_bad[threadIdx.x] |= s_bad[threadIdx.x + w];
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) e[r] = exponent_of_max(s_max[0], !s_bad[0], T);
-    } else {
-        const int r = blockIdx.x * 256 + threadIdx.x;
-        if (r >= R) return;
-        float mx = 0.0f;
-        bool bad = false;
-        for (int p = 0; p < K; ++p) {
-            const float a = fabsf(X[(int64_t)p * ld + r]);
-            if (!(a <= 3.402823466e38f)) bad = true;
-            else mx = fmaxf(mx, a);
-        }
-        e[r] = exponent_of_max(mx, !bad, T);
+    __shared__ float s_max[256];
+    __shared__ int s_bad[256];
+    const int r = blockIdx.x;
+    float mx = 0.0f;
+    int bad = 0;
+    for (int p = threadIdx.x; p < K; p += 256) {
+        const float a = fabsf(X[(int64_t)r * ld + p]);
+        if (!(a <= 3.402823466e38f)) bad = 1;   // Inf or NaN
+        else mx = fmaxf(mx, a);
     }
+    s_max[threadIdx.x] = mx;
+    s_bad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s_max[threadIdx.x] = fmaxf(s_max[threadIdx.x], s_max[threadIdx.x + w]);
+            s_bad[threadIdx.x] |= s_bad[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) e[r] = exponent_of_max(s_max[0], !s_bad[0], T);
+}
+
+// The same for vectors along the other index (element p of vector r at
+// X[p*ld + r]): workgroups of 256 vectors x `rows` values of p, neighbouring
+// threads on neighbouring addresses; the partial maxima meet in `part` by
+// integer atomic max (a non-negative float orders like its bit pattern;
+// Inf/NaN are recorded as 0xFFFFFFFF).  `part` starts at zero.
+__global__ void __launch_bounds__(256) col_max(const float *X, int64_t ld, int R, int K, int rows, u32 *part)
+{
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= R) return;
+    const int p0 = blockIdx.y * rows, p1 = min(K, p0 + rows);
+    u32 mx = 0;
+    for (int p = p0; p < p1; ++p) {
+        const float a = fabsf(X[(int64_t)p * ld + r]);
+        const u32 b = (a <= 3.402823466e38f) ? __builtin_bit_cast(u32, a) : 0xFFFFFFFFu;
+        mx = b > mx ? b : mx;
+    }
+    atomicMax(&part[r], mx);
+}
+
+__global__ void __launch_bounds__(256) col_exponents(const u32 *part, int R, int T, int *e)
+{
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= R) return;
+    const u32 b = part[r];
+    e[r] = exponent_of_max(__builtin_bit_cast(float, b == 0xFFFFFFFFu ? 0u : b), b != 0xFFFFFFFFu, T);
+}
+
+__global__ void fill_zero(u32 *p, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 // Round-to-nearest-even encoders on the FP32 bit pattern.
@@ -115,18 +134,18 @@ __device__ __forceinline__ unsigned char enc_e4m3(float y)
 
 // Q = codes of the stored rows x cols matrix X scaled by 2^-e[index], the
 // index being the element's row (BY_ROW) or column.
+// Grid: x over columns (256 per workgroup), y over rows, both strided.
 template <int FMT, bool BY_ROW>
 __global__ void __launch_bounds__(256) quantize(const float *X, int64_t ld, int rows, int cols,
                                                 const int *e, void *Q, int64_t ldq)
 {
-    const int64_t total = (int64_t)rows * cols;
-    for (int64_t t = blockIdx.x * 256ll + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
-        const int r = (int)(t / cols), c = (int)(t - (int64_t)r * cols);
-        const float y = ldexpf(X[(int64_t)r * ld + c], -e[BY_ROW ? r : c]);
-        if constexpr (FMT == 0) ((unsigned short *)Q)[(int64_t)r * ldq + c] = (unsigned short)bf16_bits(y);
-        else if constexpr (FMT == 1) ((unsigned short *)Q)[(int64_t)r * ldq + c] = enc_f16(y);
-        else ((unsigned char *)Q)[(int64_t)r * ldq + c] = enc_e4m3(y);
-    }
+    for (int r = blockIdx.y; r < rows; r += gridDim.y)
+        for (int c = blockIdx.x * 256 + threadIdx.x; c < cols; c += gridDim.x * 256) {
+            const float y = ldexpf(X[(int64_t)r * ld + c], -e[BY_ROW ? r : c]);
+            if constexpr (FMT == 0) ((unsigned short *)Q)[(int64_t)r * ldq + c] = (unsigned short)bf16_bits(y);
+            else if constexpr (FMT == 1) ((unsigned short *)Q)[(int64_t)r * ldq + c] = enc_f16(y);
+            else ((unsigned char *)Q)[(int64_t)r * ldq + c] = enc_e4m3(y);
+        }
 }
 
 // C = alpha * 2^(e_i + f_j) * P + beta * C (C not read when beta = 0; P may be C).
@@ -134,19 +153,21 @@ __global__ void __launch_bounds__(256) scale_epilogue(const float *P, int64_t ld
                                                       int64_t ldc, int m, int n, const int *e,
                                                       const int *f, float alpha, float beta)
 {
-    const int64_t total = (int64_t)m * n;
-    for (int64_t t = blockIdx.x * 256ll + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
-        const int i = (int)(t / n), j = (int)(t - (int64_t)i * n);
-        float v = alpha * ldexpf(P[(int64_t)i * ldp + j], e[i] + f[j]);
-        if (beta != 0.0f) v = fmaf(beta, C[(int64_t)i * ldc + j], v);
-        C[(int64_t)i * ldc + j] = v;
-    }
+    for (int i = blockIdx.y; i < m; i += gridDim.y)
+        for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256) {
+            float v = alpha * ldexpf(P[(int64_t)i * ldp + j], e[i] + f[j]);
+            if (beta != 0.0f) v = fmaf(beta, C[(int64_t)i * ldc + j], v);
+            C[(int64_t)i * ldc + j] = v;
+        }
 }
 
-unsigned grid_for(int64_t total)
+// 2-D grid over a rows x cols matrix: 256 columns per workgroup, one row per
+// grid row (both capped; the kernels stride).
+dim3 grid2(int64_t rows, int64_t cols)
 {
-    int64_t b = (total + 255) / 256;
-    return (unsigned)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
+    const int64_t gx = std::min<int64_t>((cols + 255) / 256, 1024);
+    const int64_t gy = std::min<int64_t>(rows, 65535);
+    return dim3((unsigned)std::max<int64_t>(gx, 1), (unsigned)std::max<int64_t>(gy, 1));
 }
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -157,21 +178,28 @@ template <int FMT>
 void launch_quantize(bool by_row, const float *X, int64_t ld, int rows, int cols, const int *e, void *Q,
                      int64_t ldq, hipStream_t s)
 {
-    const unsigned g = grid_for((int64_t)rows * cols);
+    const dim3 g = grid2(rows, cols);
     if (by_row)
-        hipLaunchKernelGGL((quantize<FMT, true>), dim3(g), dim3(256), 0, s, X, ld, rows, cols, e, Q, ldq);
+        hipLaunchKernelGGL((quantize<FMT, true>), g, dim3(256), 0, s, X, ld, rows, cols, e, Q, ldq);
     else
-        hipLaunchKernelGGL((quantize<FMT, false>), dim3(g), dim3(256), 0, s, X, ld, rows, cols, e, Q, ldq);
+        hipLaunchKernelGGL((quantize<FMT, false>), g, dim3(256), 0, s, X, ld, rows, cols, e, Q, ldq);
 }
 
-// Exponents of the R op-vectors of length K stored in X (contiguous or not).
-void launch_exponents(bool contig, const float *X, int64_t ld, int R, int K, int T, int *e, hipStream_t s)
+// Exponents of the R op-vectors of length K stored in X (contiguous or
+// not); `part` holds R words of scratch for the strided case.
+void launch_exponents(bool contig, const float *X, int64_t ld, int R, int K, int T, int *e, u32 *part,
+                      hipStream_t s)
 {
-    if (contig)
-        hipLaunchKernelGGL(vec_exponents<true>, dim3((unsigned)R), dim3(256), 0, s, X, ld, R, K, T, e);
-    else
-        hipLaunchKernelGGL(vec_exponents<false>, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, X, ld,
-                           R, K, T, e);
+    if (contig) {
+        hipLaunchKernelGGL(row_exponents, dim3((unsigned)R), dim3(256), 0, s, X, ld, K, T, e);
+        return;
+    }
+    const unsigned gx = (unsigned)((R + 255) / 256);
+    const int rows = std::max(256, (K + 65534) / 65535);   // at most 65535 slices of k
+    hipLaunchKernelGGL(fill_zero, dim3(gx), dim3(256), 0, s, part, R);
+    hipLaunchKernelGGL(col_max, dim3(gx, (unsigned)((K + rows - 1) / rows)), dim3(256), 0, s, X, ld, R,
+                       K, rows, part);
+    hipLaunchKernelGGL(col_exponents, dim3(gx), dim3(256), 0, s, part, R, T, e);
 }
 
 }  // namespace
@@ -203,18 +231,21 @@ extern "C" int gemm_scaled(char transA, char transB, int64_t m, int64_t n, int64
     const int64_t ar = ta ? k : m, ac = ta ? m : k, br = tb ? n : k, bc = tb ? k : n;
     const int64_t ldqa = round_up(ac, 16 / es), ldqb = round_up(bc, 16 / es);
     const int64_t e_bytes = round_up(m * 4, 256), f_bytes = round_up(n * 4, 256);
+    const int64_t part_bytes = e_bytes + f_bytes;   // partial maxima of strided reductions
     const int64_t qa_bytes = round_up(ar * ldqa * es, 256), qb_bytes = round_up(br * ldqb * es, 256);
     const int64_t p_bytes = beta != 0.0 ? m * n * 4 : 0;
-    char *ws = (char *)stream_workspace(d, s, (size_t)(e_bytes + f_bytes + qa_bytes + qb_bytes + p_bytes), 1);
+    char *ws = (char *)stream_workspace(
+        d, s, (size_t)(e_bytes + f_bytes + part_bytes + qa_bytes + qb_bytes + p_bytes), 1);
     if (!ws) return GEMM_E_WORKSPACE;
     int *e = (int *)ws, *f = (int *)(ws + e_bytes);
-    char *qa = ws + e_bytes + f_bytes, *qb = qa + qa_bytes;
+    u32 *part_a = (u32 *)(ws + e_bytes + f_bytes), *part_b = (u32 *)(ws + 2 * e_bytes + f_bytes);
+    char *qa = ws + e_bytes + f_bytes + part_bytes, *qb = qa + qa_bytes;
     float *P = p_bytes ? (float *)(qb + qb_bytes) : (float *)C;
     const int64_t ldp = p_bytes ? n : ldc;
     // op(A) row i: stored row i ('N', contiguous) or stored column i ('T');
     // op(B) column j: stored column j ('N') or stored row j ('T', contiguous)
-    launch_exponents(!ta, (const float *)A, lda, (int)m, (int)k, T, e, s);
-    launch_exponents(tb, (const float *)B, ldb, (int)n, (int)k, T, f, s);
+    launch_exponents(!ta, (const float *)A, lda, (int)m, (int)k, T, e, part_a, s);
+    launch_exponents(tb, (const float *)B, ldb, (int)n, (int)k, T, f, part_b, s);
     switch (fmt) {
     case 0:
         launch_quantize<0>(!ta, (const float *)A, lda, (int)ar, (int)ac, e, qa, ldqa, s);
@@ -236,7 +267,7 @@ extern "C" int gemm_scaled(char transA, char transB, int64_t m, int64_t n, int64
     }
     rc = gemm(transA, transB, m, n, k, 1.0, qa, ldqa, qb, ldqb, 0.0, P, ldp, dtype);
     if (rc != GEMM_OK) return rc;
-    hipLaunchKernelGGL(scale_epilogue, dim3(grid_for(m * n)), dim3(256), 0, s, (const float *)P, ldp,
+    hipLaunchKernelGGL(scale_epilogue, grid2(m, n), dim3(256), 0, s, (const float *)P, ldp,
                        (float *)C, ldc, (int)m, (int)n, e, f, (float)alpha, (float)beta);
     err = hipGetLastError();
     if (err != hipSuccess) {
