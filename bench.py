@@ -399,7 +399,7 @@ def grouped_bench(mg, torch, stream, reps=10):
     return out
 
 
-def serving_bench(mg, torch, rates=(2000, 5000, 10000, 20000), count=3000, warmup=300):
+def serving_bench(mg, torch, rates=(2000, 5000, 10000, 20000, 40000), count=3000, warmup=300):
     """The serving workload: Poisson arrivals, shapes as the batching workload,
     dtype mix 50% split-product FP32 / 30% BF16 / 20% INT8, 64 GiB budget;
     run by the step loop (grouped launches) and by the queue mode (one

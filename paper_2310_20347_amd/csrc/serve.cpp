@@ -154,7 +154,6 @@ class HipBackend : public Backend {
 public:
     int begin(const serve_config &cfg) override
     {
-        t0_ = std::chrono::steady_clock::now();
         hipError_t e = hipMalloc((void **)&base_, (size_t)std::max<int64_t>(cfg.budget_bytes, kAlign));
         if (e != hipSuccess) return fail(e);
         slots_per_dtype_ = cfg.inflight_steps;
@@ -167,6 +166,10 @@ public:
                     return fail(e);
             }
         }
+        // arrivals count from here: the arena and slot set-up (hundreds of
+        // milliseconds for a large arena once earlier ones were freed) is not
+        // part of any request's latency
+        t0_ = std::chrono::steady_clock::now();
         return GEMM_OK;
     }
     void end() override
