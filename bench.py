@@ -399,11 +399,14 @@ def grouped_bench(mg, torch, stream, reps=10):
     return out
 
 
-def serving_bench(mg, torch, rates=(2000, 5000, 10000, 20000, 40000), count=3000, warmup=300):
+def serving_bench(mg, torch, rates=(2000, 5000, 10000, 20000, 40000), count=20000, warmup=1000):
     """The serving workload: Poisson arrivals, shapes as the batching workload,
     dtype mix 50% split-product FP32 / 30% BF16 / 20% INT8, 64 GiB budget;
     run by the step loop (grouped launches) and by the queue mode (one
-    persistent kernel fed through a host ring), same requests."""
+    persistent kernel fed through a host ring).  The same requests at every
+    rate (only the arrival times change); each mode first serves them in
+    closed loop (one at a time) for every request's alone-latency, and each
+    rate reports the p50/p99 of latency / alone-latency."""
     from paper_2310_20347_amd import inputs
     from paper_2310_20347_amd import serve as sv
     pool_bytes = 128 << 20
@@ -412,26 +415,43 @@ def serving_bench(mg, torch, rates=(2000, 5000, 10000, 20000, 40000), count=3000
              mg.GEMM_I8: _dev_uniform(torch, (pool_bytes,), 79, "i8")}
     mix = (mg.GEMM_F32_BF16X3, mg.GEMM_BF16, mg.GEMM_I8)
     names = {mg.GEMM_F32_BF16X3: "bf16x3", mg.GEMM_BF16: "bf16", mg.GEMM_I8: "i8"}
-    out = {}
+    n = count + warmup
+    seed = inputs.seed_for(5, "serve")
+    shapes = inputs.log_uniform_shapes(n, seed)
+    kinds = inputs.categorical(n, [0.5, 0.3, 0.2], seed + 2)
+    dts = [mix[c] for c in kinds]
+
+    def requests(arrivals):
+        return [sv.Request(float(t), m, nn, k, dt, pools[dt].data_ptr(), pools[dt].data_ptr(), None)
+                for (m, nn, k), t, dt in zip(shapes, arrivals, dts)]
+
+    modes = (("step_loop", sv.serve_run), ("queue_mode", sv.serve_run_queue))
+    alone, out = {}, {"requests_per_rate": count, "warmup_requests": warmup}
+    for name, fn in modes:
+        cfg = sv.config(budget_bytes=64 << 30, max_active=512, warmup_requests=warmup, closed_loop=1)
+        rc, st, oc = fn(cfg, requests([0.0] * n))
+        alone[name] = np.array([o.latency_ms for o in oc])
+        out[f"alone_{name}"] = _serve_summary(st, names, mix)
     for rate in rates:
-        n = count + warmup
-        seed = inputs.seed_for(5, "serve") + rate
-        shapes = inputs.log_uniform_shapes(n, seed)
-        arr = inputs.poisson_arrivals(n, float(rate), seed + 1)
-        kinds = inputs.categorical(n, [0.5, 0.3, 0.2], seed + 2)
-        reqs = []
-        for (m, nn, k), t, c in zip(shapes, arr, kinds):
-            dt = mix[c]
-            reqs.append(sv.Request(float(t), m, nn, k, dt, pools[dt].data_ptr(),
-                                   pools[dt].data_ptr(), None))
+        arr = inputs.poisson_arrivals(n, float(rate), seed + 1 + rate)
+        reqs = requests(arr)
         cfg = sv.config(budget_bytes=64 << 30, max_active=512, warmup_requests=warmup)
-        rc, st, _ = sv.serve_run(cfg, reqs)
-        out[str(rate)] = _serve_summary(st, names, mix)
-        out[str(rate)]["offered_req_per_s"] = rate
-        out[str(rate)]["req_per_launch"] = round(st.mean_requests_per_launch, 2)
-        rc, st, _ = sv.serve_run_queue(cfg, reqs)
-        out[str(rate)]["queue_mode"] = _serve_summary(st, names, mix)
-        out[str(rate)]["queue_mode"]["kernel_launches"] = st.launches
+        row = {"offered_req_per_s": rate}
+        for name, fn in modes:
+            rc, st, oc = fn(cfg, reqs)
+            summ = _serve_summary(st, names, mix)
+            lat = np.array([o.latency_ms for o in oc])
+            ok = (lat >= 0) & (alone[name] > 0)
+            ok[:warmup] = False       # arrivals are increasing: the first ones are the warm-up
+            slow = lat[ok] / alone[name][ok]
+            summ["slowdown_vs_alone_p50"] = round(float(np.percentile(slow, 50)), 3)
+            summ["slowdown_vs_alone_p99"] = round(float(np.percentile(slow, 99)), 3)
+            if name == "step_loop":
+                summ["req_per_launch"] = round(st.mean_requests_per_launch, 2)
+            else:
+                summ["kernel_launches"] = st.launches
+            row[name] = summ
+        out[str(rate)] = row
     return out
 
 

@@ -11,7 +11,8 @@
  * a per-step cap, in 128x128-tile units) and launches one grouped kernel per
  * dtype on that dtype's stream; requests that arrive while steps run join the
  * next step.  A request completes when the step holding its last row panel
- * has finished; latency = completion time - arrival time.
+ * has finished; latency = completion time - arrival time (release time in
+ * closed-loop mode, see serve_config).
  *
  * Layout of a request (row-major, transA = transB = 'N', alpha = 1, beta = 0):
  * A is m x k with lda = k rounded up to a 16-byte multiple, B is k x n with
@@ -54,6 +55,13 @@ typedef struct {
                                /* queueing behind a second launch on the stream)          */
     double watchdog_s;         /* a step unfinished after this long ends the run          */
     int64_t warmup_requests;   /* first requests (by arrival) left out of the statistics  */
+    int closed_loop;           /* 0: requests arrive at their arrival times (open loop).  */
+                               /* 1: one request in the system at a time: each is        */
+                               /* released, in arrival order, at the later of its arrival */
+                               /* and the completion of the one before, and its latency   */
+                               /* counts from its release.  Serving a set of requests     */
+                               /* this way gives each one's alone-latency (on an          */
+                               /* otherwise idle GPU, same path and overheads).           */
 } serve_config;
 
 typedef struct {
@@ -71,7 +79,8 @@ typedef struct {
 
 typedef struct {
     double admit_s, done_s;   /* seconds from the start of the run (-1 if never)        */
-    double latency_ms;        /* done - arrival, -1 if the request did not complete     */
+    double latency_ms;        /* done - arrival (release, closed loop), -1 if the      */
+                              /* request did not complete                               */
     int status;               /* 0 completed, GEMM_E_SERVE failed, GEMM_E_WORKSPACE      */
                               /* rejected (does not fit the budget)                     */
 } serve_outcome;

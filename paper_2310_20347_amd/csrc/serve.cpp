@@ -58,6 +58,7 @@ struct Req {
     int64_t rows_issued = 0;
     int outstanding = 0;
     bool finished = false, failed = false, released = false, counted = false;
+    double arr_t = 0;   // latency counts from here: the arrival, or the release (closed loop)
     double admit_t = -1, done_t = -1;
     int status = 0;
     // queue mode
@@ -321,7 +322,8 @@ int check_config(const serve_config *cfg)
     if (!cfg) return -1;
     if (cfg->budget_bytes <= 0 || cfg->max_active < 1 || cfg->max_active > 8192 ||
         cfg->step_tile_budget < 1 || cfg->request_tile_cap < 1 || cfg->inflight_steps < 1 ||
-        cfg->inflight_steps > 4 || !(cfg->watchdog_s > 0) || cfg->warmup_requests < 0)
+        cfg->inflight_steps > 4 || !(cfg->watchdog_s > 0) || cfg->warmup_requests < 0 ||
+        (cfg->closed_loop != 0 && cfg->closed_loop != 1))
         return -1;
     return 0;
 }
@@ -341,6 +343,26 @@ int check_requests(int64_t count, const serve_request *reqs, bool need_src)
     return 0;
 }
 
+// Moves the requests whose arrival time has passed into the admission queue
+// (both loops).  Closed loop: at most one, and only when the system is empty
+// (nothing queued or admitted); its latency then counts from now.
+void release_arrivals(const serve_config &cfg, const std::vector<int64_t> &order, std::vector<Req> &R,
+                      double now, bool system_empty, size_t &next_arrival, std::deque<int64_t> &queue)
+{
+    while (next_arrival < order.size()) {
+        Req &r = R[(size_t)order[next_arrival]];
+        if (r.in->arrival_s > now) break;
+        if (cfg.closed_loop) {
+            if (!system_empty) break;
+            r.arr_t = now;
+            queue.push_back(order[next_arrival++]);
+            break;
+        }
+        r.arr_t = r.in->arrival_s;
+        queue.push_back(order[next_arrival++]);
+    }
+}
+
 // Outcomes and statistics of a finished run (both loops).
 void fill_stats(const serve_config &cfg, const std::vector<int64_t> &order, const std::vector<Req> &R,
                 int64_t peak_arena, int64_t peak_active, int64_t steps, int64_t launches,
@@ -358,14 +380,14 @@ void fill_stats(const serve_config &cfg, const std::vector<int64_t> &order, cons
             serve_outcome &o = outcomes[r.idx];
             o.admit_s = r.admit_t;
             o.done_s = r.finished ? r.done_t : -1.0;
-            o.latency_ms = r.finished ? 1e3 * (r.done_t - r.in->arrival_s) : -1.0;
+            o.latency_ms = r.finished ? 1e3 * (r.done_t - r.arr_t) : -1.0;
             o.status = r.finished ? 0 : (r.status ? r.status : GEMM_E_SERVE);
         }
         if ((int64_t)pos < cfg.warmup_requests || !r.finished) continue;
-        const double ms = 1e3 * (r.done_t - r.in->arrival_s);
+        const double ms = 1e3 * (r.done_t - r.arr_t);
         lat.push_back(ms);
         lat_by[r.in->dtype].push_back(ms);
-        t_first = std::min(t_first, r.in->arrival_s);
+        t_first = std::min(t_first, r.arr_t);
         t_last = std::max(t_last, r.done_t);
         flops += 2.0 * r.in->m * r.in->n * r.in->k;
     }
@@ -447,8 +469,7 @@ int run(Backend &be, const serve_config &cfg, int64_t count, const serve_request
 
     while (done < count) {
         const double now = be.now();
-        while (next_arrival < order.size() && reqs[order[next_arrival]].arrival_s <= now)
-            queue.push_back(order[next_arrival++]);
+        release_arrivals(cfg, order, R, now, queue.empty() && active.empty(), next_arrival, queue);
         // admission: FIFO, head of line waits for a slot and arena space
         while (!queue.empty() && (int64_t)active.size() < cfg.max_active) {
             Req &r = R[(size_t)queue.front()];
@@ -586,7 +607,8 @@ int run(Backend &be, const serve_config &cfg, int64_t count, const serve_request
         }
         if (!progressed && done < count) {
             double t_next = be.now() + 1e-4;
-            if (next_arrival < order.size())
+            // (closed loop: an arrival held back until the system empties is no wake-up time)
+            if (next_arrival < order.size() && (!cfg.closed_loop || (queue.empty() && active.empty())))
                 t_next = std::min(t_next, reqs[order[next_arrival]].arrival_s);
             t_next = std::min(t_next, be.completion_hint());
             be.idle_until(std::max(t_next, be.now()));
@@ -745,8 +767,7 @@ int run_queue(const serve_config &cfg, const serve_queue_config &qc, int64_t cou
     while (result == GEMM_OK && done < count) {
         const double now = now_s();
         bool progressed = false;
-        while (next_arrival < order.size() && reqs[order[next_arrival]].arrival_s <= now)
-            queue.push_back(order[next_arrival++]);
+        release_arrivals(cfg, order, R, now, queue.empty() && active == 0, next_arrival, queue);
         // admission: FIFO; a request is published at once, its operand copies
         // as the first tiles
         while (!queue.empty() && !free_slots.empty()) {

@@ -37,6 +37,27 @@ def test_single_request_latency_is_its_cost():
     assert oc[0].admit_s == pytest.approx(0.5)
 
 
+def test_closed_loop_latency_is_each_requests_alone_latency():
+    # closed loop: one request in the system at a time, latency from its
+    # release; each equals the latency of a run holding that request alone,
+    # whatever the arrival times (here a burst, all due at once)
+    shapes = inputs.log_uniform_shapes(40, seed=3)
+    dts = [mg.GEMM_F32_BF16X3, mg.GEMM_BF16, mg.GEMM_I8, mg.GEMM_F32] * 10
+    r = reqs_of(shapes, [0.0] * 40, dts)
+    rc, st, oc = sv.serve_run_sim(sv.config(closed_loop=1), r, sim())
+    assert rc == 0 and st.completed == 40
+    for i, (shape, d) in enumerate(zip(shapes, dts)):
+        _, _, solo = sv.serve_run_sim(sv.config(), reqs_of([shape], [0.0], [d]), sim())
+        assert oc[i].latency_ms == pytest.approx(solo[0].latency_ms, rel=1e-9), i
+    # released one after another, in arrival order (index order here)
+    for i in range(1, 40):
+        assert oc[i].admit_s >= oc[i - 1].done_s
+    # an open-loop run whose arrivals are far apart gives the same latencies
+    rc, _, spaced = sv.serve_run_sim(sv.config(), reqs_of(shapes, np.arange(40) * 1.0, dts), sim())
+    assert rc == 0
+    assert [o.latency_ms for o in spaced] == pytest.approx([o.latency_ms for o in oc], rel=1e-9)
+
+
 def test_budget_is_never_exceeded_and_oversize_is_rejected():
     shapes = inputs.log_uniform_shapes(300, seed=1)
     arrivals = np.sort(np.random.default_rng(2).uniform(0, 0.01, 300))
@@ -116,6 +137,7 @@ def test_invalid_configuration_and_requests():
     r = reqs_of([(8, 8, 8)], [0.0], [mg.GEMM_BF16])
     bad = sv.config(max_active=0)
     assert sv.serve_run_sim(bad, r, sim())[0] == -1
+    assert sv.serve_run_sim(sv.config(closed_loop=2), r, sim())[0] == -1
     r[0].m = 0
     assert sv.serve_run_sim(sv.config(), r, sim())[0] == -3
     assert sv.serve_run_sim(sv.config(), reqs_of([(8, 8, 8)], [0.0], [1]),
