@@ -103,10 +103,13 @@ int serve_run(const serve_config *cfg, int64_t count, const serve_request *reqs,
  * Queue mode: the same admission (FIFO, slots, arena budget) without steps.
  * One persistent kernel stays resident (one workgroup per compute unit,
  * at most half of each unit's registers) and takes work from a ring of tile
- * records in pinned host memory.  A request is published at admission as
- * copy tiles (its A and B into the arena, 256 KiB each, done by the kernel)
- * followed by its output tiles, which wait for those copies; the kernel
- * runs them between any two tiles of other requests.  A request completes
+ * records in pinned host memory, in publication order.  A request is
+ * published at admission as copy tiles (its A and B into the arena, 256 KiB
+ * each, done by the kernel) followed by the first chunk of its output tiles,
+ * which wait for those copies; its further chunks are published (oldest
+ * request first) only while fewer than backlog_tiles published tiles are
+ * unclaimed, so a request admitted later waits behind at most that backlog,
+ * not behind all of an earlier large request.  A request completes
  * when its last output tile is done; the kernel reports that through pinned
  * host memory and the host polls it.  Output tiles: 128x128 (64x64 for the
  * six-term split), the bodies of the grouped kernel's compact variant, so
@@ -116,8 +119,10 @@ int serve_run(const serve_config *cfg, int64_t count, const serve_request *reqs,
  * ring (about 4 us each) the kernel leaves, and the host relaunches it when
  * work is waiting (stats.launches counts the instances).  At the end the
  * host sets a stop word and waits for the kernel to leave.  A request whose
- * tiles do not fit the ring is rejected (GEMM_E_WORKSPACE).  stats.steps is
- * 0; mean_requests_per_launch is completed requests per kernel instance.
+ * tiles do not fit the ring is rejected (GEMM_E_WORKSPACE); a request is
+ * admitted only when the ring can take all of its tiles, so its later chunks
+ * always find room.  stats.steps is 0; mean_requests_per_launch is completed
+ * requests per kernel instance.
  */
 typedef struct {
     int64_t ring_tiles;   /* tile records in the ring: a power of two in          */
@@ -125,6 +130,11 @@ typedef struct {
     int workgroups;       /* persistent workgroups, 0 = one per compute unit;      */
                           /* larger values are reduced to that                     */
     int64_t idle_polls;   /* empty polls before the kernel leaves, 0 = 20000       */
+    int64_t chunk_tiles;  /* output tiles per published chunk, 0 = the number of    */
+                          /* workgroups                                            */
+    int64_t backlog_tiles;/* later chunks wait while this many published tiles are  */
+                          /* unclaimed, 0 = twice the number of workgroups; raised  */
+                          /* to workgroups + 17 at least                            */
 } serve_queue_config;
 
 /* Arguments: 1 cfg, 2 qcfg (NULL = defaults), 3 count, 4 reqs, 5 stats,

@@ -60,13 +60,18 @@ __device__ __forceinline__ void run_body(int body, const GemmArgs &p, int tm, in
 // The polls are relaxed loads: an acquiring load invalidates the compute
 // unit's caches and its L2 at every poll, which the workgroups still
 // computing on that XCD would pay for.  One acquire follows the wait.
-__device__ bool wait_published(int64_t t, const QCtl *ctl, QDev *dev, int64_t idle_polls)
+__device__ bool wait_published(int64_t t, QCtl *ctl, QDev *dev, int64_t idle_polls)
 {
     int64_t polls = 0, seen = -1;
     for (;;) {
         const int64_t dt = __hip_atomic_load(&dev->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (t < dt) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            // claim progress for the host's publication pacing, every 16th
+            // tile: the barrier after the claim waits for this store to reach
+            // host memory
+            if ((t & 15) == 0)
+                __hip_atomic_store(&ctl->claimed, t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             return true;
         }
         if (__hip_atomic_load(&dev->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;

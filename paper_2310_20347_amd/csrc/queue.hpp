@@ -40,13 +40,18 @@ constexpr int64_t kCopyChunk = 256 << 10;   // bytes per copy tile
 static_assert(sizeof(QTile) == 144, "tile records are 144 bytes");
 
 // Control words in pinned host memory: tail and stop written by the host,
-// fault by the kernel.
+// fault and claimed by the kernel.
 struct QCtl {
-    int64_t tail;    // tiles published
-    int32_t stop;    // set by the host when no more work will come
-    int32_t fault;   // set by the kernel: an output tile's operands never arrived
-    int32_t pad[12];
+    int64_t tail;      // tiles published
+    int32_t stop;      // set by the host when no more work will come
+    int32_t fault;     // set by the kernel: an output tile's operands never arrived
+    int64_t claimed;   // 1 + a recently claimed tile index, stored for every
+                       // 16th tile by the workgroup claiming it (stores land
+                       // in any order): fewer than 16 + workgroups behind the
+                       // claims; how far the kernel has taken the ring
+    int32_t pad[10];
 };
+static_assert(sizeof(QCtl) == 64, "control words are one 64-byte line");
 
 // Device-memory state of the queue.  claim and tail are reset by the host
 // between kernel instances; the per-slot counters reset themselves (the last

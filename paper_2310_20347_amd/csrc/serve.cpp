@@ -64,6 +64,9 @@ struct Req {
     // queue mode
     int qslot = -1, qgen = 0;
     int64_t qtiles = 0, qcopies = 0;
+    int64_t qpub = 0;      // output tiles published so far
+    int64_t qfirst = -1;   // ring position of the request's first tile
+    GemmArgs qargs;        // its output tiles' arguments
     double publish_t = -1;
 };
 
@@ -717,6 +720,12 @@ int run_queue(const serve_config &cfg, const serve_queue_config &qc, int64_t cou
     // at most one workgroup per compute unit: the result copies (and any
     // other work on the device) need the rest of each unit's registers
     const int grid = qc.workgroups > 0 ? std::min(qc.workgroups, cus) : cus;
+    const int64_t chunk = qc.chunk_tiles > 0 ? qc.chunk_tiles : grid;
+    // the claimed word trails the claims by fewer than 16 + grid (it is
+    // stored for every 16th tile, and the claiming workgroups' stores land in
+    // any order), so a smaller backlog could read as full with every tile taken
+    const int64_t backlog = std::max<int64_t>(qc.backlog_tiles > 0 ? qc.backlog_tiles : 2 * (int64_t)grid,
+                                              (int64_t)grid + 17);
     QueueRes q;
     int rc = q.init(cfg, ring);
     if (rc != GEMM_OK) {
@@ -745,11 +754,43 @@ int run_queue(const serve_config &cfg, const serve_queue_config &qc, int64_t cou
     Arena arena;
     arena.init(cfg.budget_bytes);
     std::deque<int64_t> queue;
-    std::vector<int64_t> published;
+    std::vector<int64_t> published;   // admitted, not finished
+    std::deque<int64_t> partial;      // admitted with output tiles still to publish, oldest first
     std::vector<int> free_slots, slot_gen((size_t)cfg.max_active, 0);
     for (int i = cfg.max_active - 1; i >= 0; --i) free_slots.push_back(i);
     size_t next_arrival = 0;
-    int64_t done = 0, peak_active = 0, active = 0, tail = 0, completed_tiles = 0;
+    int64_t done = 0, peak_active = 0, active = 0, tail = 0;
+    int64_t unpublished = 0;   // output tiles of admitted requests not yet published
+    int64_t claimed_seen = -1;
+    double claimed_t = 0;      // when the claimed word last changed
+
+    // Ring positions below the watermark hold records of finished requests
+    // only (each of which was read before its tile ran), so the host may
+    // overwrite them.  Admission keeps tail + unpublished <= watermark + ring,
+    // so every later chunk of an admitted request has room.
+    auto watermark = [&]() {
+        int64_t w = tail;
+        for (int64_t i : published) w = std::min(w, R[(size_t)i].qfirst);
+        return w;
+    };
+    auto put_outputs = [&](Req &r, int64_t count) {
+        int64_t pos = tail;
+        for (int64_t t = r.qpub; t < r.qpub + count; ++t) {
+            QTile &rec = q.ring_h[pos++ & (ring - 1)];
+            rec.a = r.qargs;
+            rec.t = (int)t;
+            rec.slot = r.qslot;
+            rec.ntiles = (int)r.qtiles;
+            rec.body = kclass_of(r.in->dtype, r.in->k);
+            rec.gen = r.qgen;
+            rec.kind = 0;
+            rec.ncopy = (int)r.qcopies;
+            rec.pad = 0;
+        }
+        r.qpub += count;
+        unpublished -= count;
+        tail = pos;
+    };
 
     auto finish = [&](Req &r) {
         ++done;
@@ -778,7 +819,7 @@ int run_queue(const serve_config &cfg, const serve_queue_config &qc, int64_t cou
                 finish(r);
                 continue;
             }
-            if (tail + r.qtiles + r.qcopies - completed_tiles > ring) break;   // ring full
+            if (tail + unpublished + r.qcopies + r.qtiles > watermark() + ring) break;   // ring full
             const int64_t off = arena.alloc(r.bytes);
             if (off < 0) break;
             queue.pop_front();
@@ -790,6 +831,7 @@ int run_queue(const serve_config &cfg, const serve_queue_config &qc, int64_t cou
             r.qgen = ++slot_gen[(size_t)r.qslot];
             const int es = in_bytes(r.in->dtype);
             int64_t pos = tail;
+            r.qfirst = tail;
             auto put_copies = [&](const void *src, char *dst, int64_t bytes) {
                 for (int64_t o = 0; o < bytes; o += kCopyChunk) {
                     QTile &rec = q.ring_h[pos++ & (ring - 1)];
@@ -826,23 +868,43 @@ int run_queue(const serve_config &cfg, const serve_queue_config &qc, int64_t cou
             a.order = 0;
             a.group = 8;
             a.terms = split_terms(kclass);
-            for (int64_t t = 0; t < r.qtiles; ++t) {
-                QTile &rec = q.ring_h[pos++ & (ring - 1)];
-                rec.a = a;
-                rec.t = (int)t;
-                rec.slot = r.qslot;
-                rec.ntiles = (int)r.qtiles;
-                rec.body = kclass;
-                rec.gen = r.qgen;
-                rec.kind = 0;
-                rec.ncopy = (int)r.qcopies;
-                rec.pad = 0;
-            }
+            r.qargs = a;
             tail = pos;
+            // the first chunk now; the rest as the kernel takes the ring
+            r.qpub = 0;
+            unpublished += r.qtiles;
+            put_outputs(r, std::min(chunk, r.qtiles));
+            if (r.qpub < r.qtiles) partial.push_back(r.idx);
             __atomic_store_n(&q.ctl_h->tail, tail, __ATOMIC_RELEASE);
             r.publish_t = now_s();
             published.push_back(r.idx);
             progressed = true;
+        }
+        // later chunks, oldest request first, while the unclaimed backlog is
+        // short; should the claimed word stand still for 100 us (its stores
+        // are not ordered, so it could rest below the claims) one chunk goes
+        // out regardless, so progress never depends on it
+        if (!partial.empty()) {
+            const int64_t claimed = __atomic_load_n(&q.ctl_h->claimed, __ATOMIC_ACQUIRE);
+            if (claimed != claimed_seen) {
+                claimed_seen = claimed;
+                claimed_t = now;
+            }
+            bool put = false, force = now - claimed_t > 100e-6;
+            while (!partial.empty() && (tail - claimed < backlog || force)) {
+                Req &r = R[(size_t)partial.front()];
+                put_outputs(r, std::min(chunk, r.qtiles - r.qpub));
+                if (r.qpub >= r.qtiles) partial.pop_front();
+                put = true;
+                if (force) {
+                    force = false;
+                    claimed_t = now;
+                }
+            }
+            if (put) {
+                __atomic_store_n(&q.ctl_h->tail, tail, __ATOMIC_RELEASE);
+                progressed = true;
+            }
         }
         if (__atomic_load_n(&q.ctl_h->fault, __ATOMIC_ACQUIRE)) {
             result = GEMM_E_SERVE;
@@ -864,7 +926,6 @@ int run_queue(const serve_config &cfg, const serve_queue_config &qc, int64_t cou
                         r.status = GEMM_E_SERVE;
                     }
                 }
-                completed_tiles += r.qtiles + r.qcopies;
                 finish(r);
                 published[i] = published.back();
                 published.pop_back();
@@ -967,7 +1028,8 @@ int serve_run_queue(const serve_config *cfg, const serve_queue_config *qcfg, int
     if (qcfg) qc = *qcfg;
     if (qc.ring_tiles < 0 || (qc.ring_tiles > 0 && (qc.ring_tiles < 1024 || qc.ring_tiles > (1 << 24) ||
                                                     (qc.ring_tiles & (qc.ring_tiles - 1)))) ||
-        qc.workgroups < 0 || qc.workgroups > 8192 || qc.idle_polls < 0)
+        qc.workgroups < 0 || qc.workgroups > 8192 || qc.idle_polls < 0 || qc.chunk_tiles < 0 ||
+        qc.backlog_tiles < 0)
         return -2;
     int v = check_requests(count, reqs, true);
     if (v) return v - 1;

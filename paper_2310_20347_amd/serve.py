@@ -46,7 +46,8 @@ class Outcome(ctypes.Structure):
 
 
 class QueueConfig(ctypes.Structure):
-    _fields_ = [("ring_tiles", _I64), ("workgroups", _INT), ("idle_polls", _I64)]
+    _fields_ = [("ring_tiles", _I64), ("workgroups", _INT), ("idle_polls", _I64),
+                ("chunk_tiles", _I64), ("backlog_tiles", _I64)]
 
 
 class Sim(ctypes.Structure):
@@ -130,8 +131,9 @@ def serve_run_sim(cfg: Config, reqs: Sequence[Any], sim: Sim, check: bool = Fals
     return rc, st, list(oc)[:len(reqs)]
 
 
-def queue_config(ring_tiles=0, workgroups=0, idle_polls=0) -> QueueConfig:
-    return QueueConfig(ring_tiles, workgroups, idle_polls)
+def queue_config(ring_tiles=0, workgroups=0, idle_polls=0, chunk_tiles=0,
+                 backlog_tiles=0) -> QueueConfig:
+    return QueueConfig(ring_tiles, workgroups, idle_polls, chunk_tiles, backlog_tiles)
 
 
 def serve_run_queue(cfg: Config, reqs: Sequence[Any], qcfg: Optional[QueueConfig] = None,

@@ -43,3 +43,34 @@ def test_queue_idle_exit_and_relaunch_lose_no_work():
     assert rc == 0 and st.completed == 120 and st.failed == 0
     assert st.launches > 1
     assert check_results(pools, meta) >= 25
+
+
+def test_queue_chunked_publication_and_ring_wrap():
+    # chunks of 8 output tiles and a 1024-record ring: large requests are
+    # published over many chunks while later requests interleave, and the
+    # ring wraps many times (records are rewritten only below the watermark
+    # of unfinished requests); a closed-loop pass over the same requests
+    # checks the one-at-a-time release as well
+    mg.gemm_init(None)
+    pools = Pools(64 << 20, seed=9301)
+    # up to 1024^3: at most 256 output tiles + 32 copy tiles per request, so
+    # every request fits the ring and the ring wraps many times over the run
+    reqs, meta = workload(300, 8000.0, 9302, pools, lo=16, hi=1024, result_every=6)
+    cfg = sv.config(budget_bytes=2 << 30, max_active=128, watchdog_s=20.0)
+    q = sv.queue_config(ring_tiles=1024, chunk_tiles=8)
+    print("queue mode, chunks of 8 tiles, ring 1024: 300 requests at 8k req/s", flush=True)
+    rc, st, oc = sv.serve_run_queue(cfg, reqs, q)
+    print(f"completed {st.completed} p99 {st.p99_ms:.3f} ms", flush=True)
+    assert rc == 0 and st.completed == 300 and st.failed == 0 and st.rejected == 0
+    assert all(o.status == 0 for o in oc)
+    assert check_results(pools, meta) >= 45
+    for md in meta:
+        if md["result"] is not None:
+            md["result"][:] = 0
+    cfg1 = sv.config(budget_bytes=2 << 30, max_active=128, watchdog_s=20.0, closed_loop=1)
+    print("the same requests in closed loop", flush=True)
+    rc, st1, oc1 = sv.serve_run_queue(cfg1, reqs, q)
+    assert rc == 0 and st1.completed == 300 and st1.failed == 0
+    for a, b in zip(oc1[1:], oc1[:-1]):   # arrivals are increasing: index order
+        assert a.admit_s >= b.done_s
+    assert check_results(pools, meta) >= 45

@@ -151,5 +151,7 @@ def test_queue_mode_rejects_invalid_arguments_before_touching_the_device():
     assert sv.serve_run_queue(sv.config(), r, sv.queue_config(ring_tiles=512), check=False)[0] == -2
     assert sv.serve_run_queue(sv.config(), r, sv.queue_config(idle_polls=-1), check=False)[0] == -2
     assert sv.serve_run_queue(sv.config(), r, sv.queue_config(workgroups=-3), check=False)[0] == -2
+    assert sv.serve_run_queue(sv.config(), r, sv.queue_config(chunk_tiles=-1), check=False)[0] == -2
+    assert sv.serve_run_queue(sv.config(), r, sv.queue_config(backlog_tiles=-1), check=False)[0] == -2
     r[0].m = 0
     assert sv.serve_run_queue(sv.config(), r, check=False)[0] == -4
