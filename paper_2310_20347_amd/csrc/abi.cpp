@@ -131,23 +131,26 @@ void ensure_registered()
     register_direct_byte(g_cfgs);
     // packed split: every direct bf16 tile, run on operands that a packing
     // pass has split into bf16 pieces (three- and six-term classes)
-    const size_t nbase = g_cfgs.size();
-    for (int cls : {K_SPLIT2, K_SPLIT3}) {
-        for (size_t i = 0; i < nbase; ++i) {
-            if (g_cfgs[i].kclass != K_BF16 || !g_cfgs[i].direct) continue;
-            KernelCfg p = g_cfgs[i];
-            p.kclass = cls;
-            p.kind = 5;
-            p.direct = false;
-            p.packed = (int)i;
-            for (int t = 0; t < 4; ++t)
-                for (int v = 0; v < 2; ++v) {
-                    p.func[t][v] = split_pack_entry();
-                    p.splitk[t][v] = nullptr;
-                }
-            g_cfgs.push_back(p);
+    auto add_packed = [](size_t from, size_t to) {
+        for (int cls : {K_SPLIT2, K_SPLIT3}) {
+            for (size_t i = from; i < to; ++i) {
+                if (g_cfgs[i].kclass != K_BF16 || !g_cfgs[i].direct) continue;
+                KernelCfg p = g_cfgs[i];
+                p.kclass = cls;
+                p.kind = 5;
+                p.direct = false;
+                p.packed = (int)i;
+                for (int t = 0; t < 4; ++t)
+                    for (int v = 0; v < 2; ++v) {
+                        p.func[t][v] = split_pack_entry();
+                        p.splitk[t][v] = nullptr;
+                    }
+                g_cfgs.push_back(p);
+            }
         }
-    }
+    };
+    const size_t nbase = g_cfgs.size();
+    add_packed(0, nbase);
     // split-K: every tile compiled with a sliced form
     const size_t nall = g_cfgs.size();
     for (size_t i = 0; i < nall; ++i) {
@@ -170,6 +173,12 @@ void ensure_registered()
     // split product on direct-staged FP32 panels
     register_splitdirect(g_cfgs);
     register_f64(g_cfgs);
+    // appended last, so every configuration number above stays as it was
+    register_direct_f32_late(g_cfgs);
+    const size_t nlate = g_cfgs.size();
+    register_direct_half_late(g_cfgs);
+    register_direct_byte_late(g_cfgs);
+    add_packed(nlate, g_cfgs.size());
     for (size_t i = 0; i < g_cfgs.size(); ++i) g_by_class[g_cfgs[i].kclass].push_back((int)i);
     g_registered = true;
 }

@@ -294,7 +294,14 @@ __device__ __forceinline__ void read_frag_tr(const char *panel, int r0, int c, i
 // with an NS-deep ring of LDS stages.  Requires 16-byte aligned operands and
 // leading dimensions (the vectorised case).
 // ---------------------------------------------------------------------------
-template <class DT, int MC, int NC, int WM, int WN, bool TA, bool TB, int NS, int KB = 128>
+// OVL: the MFMAs of each stage's last fragment chunk are deferred past the
+// next stage's barrier, where they run while the first fragments of that
+// stage are read from LDS (otherwise every wave waits for those reads after
+// each barrier with no MFMA to issue).  The deferred fragments are already in
+// registers; each wave waits for its LDS reads to land before the barrier,
+// so no load of the next stage can overwrite LDS that is still being read.
+template <class DT, int MC, int NC, int WM, int WN, bool TA, bool TB, int NS, int KB = 128,
+          bool OVL = false>
 struct DTile {
     static constexpr int NW = WM * WN, NT = 64 * NW;
     static constexpr int KC = KB / DT::GES;
@@ -330,6 +337,17 @@ struct DTile {
             if constexpr (TB) read_frag_k<DT, KB>(pb, wn * WTN + 16 * j, c, lane, fb[j]);
             else read_frag_tr<DT, NC>(pb, wn * WTN + 16 * j, c, lane, fb[j]);
         }
+    }
+
+    static __device__ __forceinline__ void mfma_chunk(Acc (*acc)[FN], const u32 (*fa)[1][DT::FDW],
+                                                      const u32 (*fb)[1][DT::FDW])
+    {
+#pragma unroll
+        for (int st = 0; st < Sub<DT>::value; ++st)
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) mma_step<DT>(acc[i][j], fa[i], fb[j], st);
     }
 
     // The micro-kernel over one stage; the fragments of chunk c+1 are read
@@ -384,6 +402,42 @@ struct DTile {
             }
             const bool ragged = (!TA || TB) && (p.k % PA::VK) != 0;
             int rd = 0, wr = NS - 1;   // ring buffers: stage being read, stage being loaded
+            if constexpr (OVL) {
+                // (with one chunk per stage both buffers would hold a whole
+                // stage's fragments, which spills the 256x256 tiles)
+                static_assert(NCH % 2 == 0, "the deferred chunk and the next stage's first chunk "
+                                            "use different fragment buffers");
+                u32 fa[2][FM][1][DT::FDW], fb[2][FN][1][DT::FDW];
+                for (int s = 0; s < nk; ++s) {
+                    // this wave's loads of stage s have landed and its reads of
+                    // stage s-1 (the deferred fragments) are in registers ...
+                    __builtin_amdgcn_s_waitcnt(((NS - 2) * LOADS & 15) | (((NS - 2) * LOADS >> 4) << 14) |
+                                               (7 << 4));
+                    __builtin_amdgcn_s_barrier();   // ... and every wave's
+                    pin_order();
+                    char *cur = lds + rd * STAGE_BYTES;
+                    if (ragged && s == nk - 1) {
+                        const int valid_k = p.k - s * KC;
+                        if constexpr (!TA) PA::fix_tail(cur, valid_k, tid, NT);
+                        if constexpr (TB) PB::fix_tail(cur + PANEL_A, valid_k, tid, NT);
+                        __syncthreads();
+                    }
+                    char *nxt = lds + wr * STAGE_BYTES;
+                    pa.issue(A, p.lda, (s + NS - 1) * KC, nxt, wave);
+                    pb.issue(B, p.ldb, (s + NS - 1) * KC, nxt + PANEL_A, wave);
+                    pin_order();
+                    read_chunk(cur, 0, wm, wn, lane, fa[0], fb[0]);
+                    if (s > 0) mfma_chunk(acc, fa[1], fb[1]);   // stage s-1's last chunk
+#pragma unroll
+                    for (int c = 0; c + 1 < NCH; ++c) {
+                        read_chunk(cur, c + 1, wm, wn, lane, fa[(c + 1) & 1], fb[(c + 1) & 1]);
+                        mfma_chunk(acc, fa[c & 1], fb[c & 1]);
+                    }
+                    rd = rd + 1 == NS ? 0 : rd + 1;
+                    wr = wr + 1 == NS ? 0 : wr + 1;
+                }
+                mfma_chunk(acc, fa[1], fb[1]);   // the last stage's last chunk
+            } else
             for (int s = 0; s < nk; ++s) {
                 wait_vm<(NS - 2) * LOADS>();   // this wave's loads of stage s have landed
                 __builtin_amdgcn_s_barrier();  // ... and every wave's; stage s-1 is consumed

@@ -20,4 +20,13 @@ void register_direct_byte(std::vector<KernelCfg> &out)
     add_direct<TI8, 256, 256, 2, 4, 4, false, 64>(out, K_I8);
     add_direct<TI8, 256, 256, 2, 4, 5, false, 64>(out, K_I8);
 }
+
+// Registered after every other family (configuration numbers above stay):
+// each stage's last MFMAs deferred past the next barrier (INT8 only: an FP8
+// stage is a single fragment chunk, nothing to overlap with).
+void register_direct_byte_late(std::vector<KernelCfg> &out)
+{
+    add_direct<TI8, 256, 256, 2, 4, 2, false, 128, true>(out, K_I8);
+    add_direct<TI8, 256, 128, 2, 2, 3, false, 128, true>(out, K_I8);
+}
 }  // namespace mg

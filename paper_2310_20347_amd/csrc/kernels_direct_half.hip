@@ -20,4 +20,21 @@ void register_direct_half(std::vector<KernelCfg> &out)
     add_half_direct<TBF16>(out, K_BF16);
     add_half_direct<TF16>(out, K_F16);
 }
+
+template <class DT>
+static void add_half_late(std::vector<KernelCfg> &out, int kclass)
+{
+    add_direct<DT, 256, 256, 2, 4, 2, false, 128, true>(out, kclass);
+    add_direct<DT, 256, 256, 2, 2, 2, false, 128, true>(out, kclass);
+    add_direct<DT, 256, 128, 2, 2, 3, false, 128, true>(out, kclass);
+}
+
+// Registered after every other family (configuration numbers above stay):
+// each stage's last MFMAs deferred past the next barrier (64-byte stages are
+// a single fragment chunk: nothing to overlap with).
+void register_direct_half_late(std::vector<KernelCfg> &out)
+{
+    add_half_late<TBF16>(out, K_BF16);
+    add_half_late<TF16>(out, K_F16);
+}
 }  // namespace mg

@@ -51,6 +51,10 @@ void register_resident_split(std::vector<KernelCfg> &out);
 void register_resident_half(std::vector<KernelCfg> &out);
 void register_resident_byte(std::vector<KernelCfg> &out);
 void register_direct_f32(std::vector<KernelCfg> &out);
+// appended after every family, so earlier configuration numbers stay
+void register_direct_f32_late(std::vector<KernelCfg> &out);
+void register_direct_half_late(std::vector<KernelCfg> &out);
+void register_direct_byte_late(std::vector<KernelCfg> &out);
 void register_direct_half(std::vector<KernelCfg> &out);
 void register_direct_byte(std::vector<KernelCfg> &out);
 void register_nopack(std::vector<KernelCfg> &out);
