@@ -230,8 +230,87 @@ def extras(mg, torch, stream, ops):
                           "bf16x3_tflops": round(flops / tot_x3 / 1e9, 2),
                           "bf16x3_speedup_vs_f32": round(tot_f32 / tot_x3, 3)}
     res["precision_8192"] = precision_8192(mg, torch, stream)
+    res["accuracy_8192"] = accuracy_8192(mg, torch, stream)
     res["packing_configs"] = packing_configs(mg, torch, stream)
     return res
+
+
+# Error limits of the graded metric max|C - C_ref| / (k max|A| max|B|) (C_ref
+# in FP64 from the FP32 source values, so input rounding counts): FP32 and
+# the FP32-accurate split 2e-6, BF16 / FP16 8e-3, FP8 the e4m3 unit
+# roundoff 2^-4 (no limit is given for it; reported against this bound).
+ERR_LIMITS = {"f32": 2e-6, "bf16x3": 2e-6, "bf16x6": 2e-6, "bf16": 8e-3, "f16": 8e-3,
+              "e4m3": 6.25e-2, "f16_scaled": 8e-3, "e4m3_scaled": 6.25e-2}
+
+
+def accuracy_8192(mg, torch, stream, rows=16):
+    """Error of every float path at 8192^3 on N(0,1) and on badly scaled
+    inputs (Dr X0 Dc with diagonal entries 2^U[-20,20]), over a band of `rows`
+    rows of C spread over m, against an FP64 product of the FP32 source rows
+    (plain numpy): the graded metric, and the componentwise error
+    max |C - C_ref| / (|A||B|) that the badly scaled case calls for.  INT8:
+    the sampled rows equal the exact int64 product.  A path whose output is
+    not finite (unscaled FP16/FP8 overflow on badly scaled data) reports
+    null."""
+    from paper_2310_20347_amd import inputs
+    n = 8192
+    sel = np.arange(rows) * (n // rows) + (np.arange(rows) * 37) % (n // rows)
+    sel_t = torch.from_numpy(sel).cuda()
+    out = {}
+    for dist in ("normal", "badly_scaled"):
+        if dist == "normal":
+            a32 = inputs.normal((n, n), inputs.seed_for(3, "A"))
+            b32 = inputs.normal((n, n), inputs.seed_for(3, "B"))
+        else:
+            a32 = inputs.badly_scaled(n, n, inputs.seed_for(3, "A") + 5)
+            b32 = inputs.badly_scaled(n, n, inputs.seed_for(3, "B") + 5)
+        b64 = b32.astype(np.float64)
+        a_rows = a32[sel].astype(np.float64)
+        ref = a_rows @ b64
+        mag = np.abs(a_rows) @ np.abs(b64)
+        del b64
+        scale = n * float(np.abs(a32).max()) * float(np.abs(b32).max())
+        Cd = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        res = {}
+        for name, dt, enc, scaled in (
+                ("f32", mg.GEMM_F32, None, False), ("bf16x3", mg.GEMM_F32_BF16X3_ONLY, None, False),
+                ("bf16x6", mg.GEMM_F32_BF16X6, None, False),
+                ("bf16", mg.GEMM_BF16, inputs.to_bf16_bits, False),
+                ("f16", mg.GEMM_F16, inputs.to_f16_bits, False),
+                ("e4m3", mg.GEMM_F8E4M3, inputs.to_e4m3_bits, False),
+                ("f16_scaled", mg.GEMM_F16, None, True), ("e4m3_scaled", mg.GEMM_F8E4M3, None, True)):
+            if enc is None:
+                Ad, Bd = torch.from_numpy(a32).cuda(), torch.from_numpy(b32).cuda()
+            elif enc is inputs.to_e4m3_bits:
+                Ad, Bd = torch.from_numpy(enc(a32)).cuda(), torch.from_numpy(enc(b32)).cuda()
+            else:
+                Ad = torch.from_numpy(enc(a32).view(np.int16)).cuda()
+                Bd = torch.from_numpy(enc(b32).view(np.int16)).cuda()
+            fn = mg.gemm_scaled if scaled else mg.gemm
+            fn("N", "N", n, n, n, 1.0, Ad, n, Bd, n, 0.0, Cd, n, dt, stream=stream)
+            C = Cd.index_select(0, sel_t).cpu().numpy().astype(np.float64)
+            del Ad, Bd
+            if not np.all(np.isfinite(C)):
+                res[name] = {"err": None, "componentwise": None, "limit": ERR_LIMITS[name],
+                             "within": False, "note": "non-finite output"}
+                continue
+            d = np.abs(C - ref)
+            err = float(d.max() / scale)
+            comp = float((d / np.maximum(mag, np.finfo(np.float64).tiny)).max())
+            res[name] = {"err": float(f"{err:.3e}"), "componentwise": float(f"{comp:.3e}"),
+                         "limit": ERR_LIMITS[name], "within": err <= ERR_LIMITS[name]}
+        out[dist] = res
+        del Cd
+        torch.cuda.empty_cache()
+    ai = inputs.int8_uniform((n, n), 41)
+    bi = inputs.int8_uniform((n, n), 42)
+    Ci = torch.empty((n, n), dtype=torch.int32, device="cuda")
+    mg.gemm("N", "N", n, n, n, 1, torch.from_numpy(ai).cuda(), n, torch.from_numpy(bi).cuda(), n, 0, Ci, n,
+            mg.GEMM_I8, stream=stream)
+    exact = ai[sel].astype(np.int64) @ bi.astype(np.int64)
+    out["i8_rows_exact"] = bool(np.array_equal(Ci.index_select(0, sel_t).cpu().numpy().astype(np.int64), exact))
+    out["rows_checked"] = rows
+    return out
 
 
 def precision_8192(mg, torch, stream):
