@@ -116,7 +116,8 @@ int gemm(char transA, char transB, int64_t m, int64_t n, int64_t k,
  * than the format holds (A = Dr A0 Dc with diagonal scalings over 2^+-20,
  * say), where the plain FP16 and FP8 paths overflow or flush to zero.  The
  * quantised operands live in a second per-stream workspace of about
- * (m*k + k*n)*bytes + 4*(m + n) bytes (+ 4*m*n when beta != 0); if it
+ * (m*k + k*n)*bytes + 8*(m + n) bytes (exponents and the partial maxima of
+ * the strided exponent reductions; + 4*m*n when beta != 0); if it
  * cannot grow (allocation failure, or during a graph capture) the call
  * returns GEMM_E_WORKSPACE.  Asynchronous on the current stream like gemm().
  */
