@@ -179,6 +179,7 @@ void ensure_registered()
     register_direct_half_late(g_cfgs);
     register_direct_byte_late(g_cfgs);
     add_packed(nlate, g_cfgs.size());
+    register_f64_late(g_cfgs);
     for (size_t i = 0; i < g_cfgs.size(); ++i) g_by_class[g_cfgs[i].kclass].push_back((int)i);
     g_registered = true;
 }

@@ -106,4 +106,16 @@ void register_f64(std::vector<KernelCfg> &out)
     add_direct<TF64, 64, 64, 2, 2, 3>(out, K_F64);
 }
 
+// Registered after every other family, so the configuration numbers above
+// (and the tuning tables that name them) stay as they were: each stage's last
+// MFMAs deferred past the next barrier (a stage holds 16 values of k, so the
+// barrier and the first fragment reads weigh more than in the 16-bit tiles).
+void register_f64_late(std::vector<KernelCfg> &out)
+{
+    add_direct<TF64, 64, 64, 2, 2, 2, false, 128, true>(out, K_F64);
+    add_direct<TF64, 64, 64, 2, 2, 3, false, 128, true>(out, K_F64);
+    add_direct<TF64, 128, 64, 2, 2, 2, false, 128, true>(out, K_F64);
+    add_direct<TF64, 128, 128, 2, 2, 2, false, 128, true>(out, K_F64);
+}
+
 }  // namespace mg

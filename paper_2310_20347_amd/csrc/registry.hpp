@@ -55,6 +55,7 @@ void register_direct_f32(std::vector<KernelCfg> &out);
 void register_direct_f32_late(std::vector<KernelCfg> &out);
 void register_direct_half_late(std::vector<KernelCfg> &out);
 void register_direct_byte_late(std::vector<KernelCfg> &out);
+void register_f64_late(std::vector<KernelCfg> &out);
 void register_direct_half(std::vector<KernelCfg> &out);
 void register_direct_byte(std::vector<KernelCfg> &out);
 void register_nopack(std::vector<KernelCfg> &out);
