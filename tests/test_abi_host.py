@@ -154,3 +154,24 @@ def test_analytical_model_structure():
     ranked = sorted(range(mg.num_configs(mg.GEMM_F32)),
                     key=lambda c: mg.model_us(mg.GEMM_F32, c, 196, 1024, 4608))
     assert mg.config_info(mg.GEMM_F32, ranked[0])["kind"] == 6
+
+
+def test_shipped_tuning_table_names_existing_configurations():
+    """Configurations are only ever appended to a class, so the shipped table
+    keeps naming the tiles it was tuned on: every entry's configuration exists
+    in its class and has an 'N','N' kernel (the layout the tuner times)."""
+    import json
+    path = os.path.join(os.path.dirname(os.path.abspath(mg.__file__)), "mgemm_tune.json")
+    table = json.load(open(path))
+    assert table["arch"].startswith("gfx950")
+    family = {0: mg.GEMM_F32, 1: mg.GEMM_F32_BF16X3_ONLY, 2: mg.GEMM_F32_BF16X6, 3: mg.GEMM_BF16,
+              4: mg.GEMM_F16, 5: mg.GEMM_F8E4M3, 6: mg.GEMM_I8, 7: mg.GEMM_F64}
+    seen = set()
+    for e in table["entries"]:
+        dt = family[e["kclass"]]
+        assert 0 <= e["cfg"] < mg.num_configs(dt), e
+        assert mg.config_supports(dt, e["cfg"], "N", "N"), e
+        assert e["order"] in (0, 1) and e["group"] > 0 and e["us"] > 0, e
+        assert all(4 <= e[b] <= 12 for b in ("bm", "bn", "bk")), e
+        seen.add(e["kclass"])
+    assert seen == set(family)
