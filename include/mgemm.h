@@ -95,9 +95,13 @@ enum {
  *   dtype unknown; for GEMM_I8, alpha (-6) or beta (-11) not an int32 integer.
  *   The loop order, the block sizes (mc, nc, kc) and the MFMA wave tile are
  *   chosen per (dtype, trans, size bucket) from the tuning table (gemm_init).
- *   Packed split and split-K configurations use a library-owned workspace
- *   per stream that grows (allocates) when a call needs more than it holds;
- *   if it cannot grow, the call runs an unsliced / fused configuration.
+ *   Packed split and split-K configurations use the workspace reserved for
+ *   the calling thread's stream (gemm_init, gemm_reserve_workspace); gemm()
+ *   itself never allocates, frees or synchronises.  When the reservation is
+ *   smaller than the chosen configuration needs (gemm_workspace_bytes), the
+ *   call runs the class's configuration that needs none (the unsliced tile
+ *   for split-K, the fused split tile for the packed split); the result is
+ *   equal to the oracle's at the same tolerance either way.
  */
 int gemm(char transA, char transB, int64_t m, int64_t n, int64_t k,
          double alpha, const void *A, int64_t lda, const void *B, int64_t ldb,
@@ -115,15 +119,22 @@ int gemm(char transA, char transB, int64_t m, int64_t n, int64_t k,
  * values return -14.  For data whose rows and columns span more magnitudes
  * than the format holds (A = Dr A0 Dc with diagonal scalings over 2^+-20,
  * say), where the plain FP16 and FP8 paths overflow or flush to zero.  The
- * quantised operands live in a second per-stream workspace of about
- * (m*k + k*n)*bytes + 8*(m + n) bytes (exponents and the partial maxima of
- * the strided exponent reductions; + 4*m*n when beta != 0); if it
- * cannot grow (allocation failure, or during a graph capture) the call
- * returns GEMM_E_WORKSPACE.  Asynchronous on the current stream like gemm().
+ * quantised operands live in the stream's second reserved workspace, of
+ * gemm_scaled_workspace_bytes() bytes: about (m*k + k*n)*bytes + 16*(m + n)
+ * (exponents and the partial maxima of the strided exponent reductions;
+ * + 4*m*n when beta != 0).  When the reservation is smaller the call returns
+ * GEMM_E_WORKSPACE and launches nothing; it never allocates.  Asynchronous on
+ * the current stream like gemm().  Argument errors follow gemm(), with
+ * argument 14 (dtype) checked after the others.
  */
 int gemm_scaled(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha,
                 const void *A, int64_t lda, const void *B, int64_t ldb, double beta, void *C,
                 int64_t ldc, int dtype);
+
+/* Bytes of the scaled path's workspace one gemm_scaled call of these sizes
+ * needs; -1 for invalid sizes or a dtype gemm_scaled does not take. */
+int64_t gemm_scaled_workspace_bytes(char transA, char transB, int64_t m, int64_t n, int64_t k,
+                                    double beta, int dtype);
 
 /* One problem of a grouped call; the fields mean what gemm()'s arguments do. */
 typedef struct {
@@ -193,14 +204,42 @@ int gemm_set_stream(void *hip_stream);
 
 /*
  * Initialise the library on the current device: query the device, register
- * the compiled kernel family and load the tuning table from
- * `tune_table_path` (JSON written by gemm_tune; NULL or "" = built-in
- * defaults, or the path in the MGEMM_TUNE_TABLE environment variable).
- * Optional: the first gemm call on a device initialises lazily with defaults,
- * but that first call allocates, so call gemm_init before any graph capture.
+ * the compiled kernel family, load the tuning table from `tune_table_path`
+ * (JSON written by gemm_tune; NULL or "" = built-in defaults, or the path in
+ * the MGEMM_TUNE_TABLE environment variable), allocate the grouped launch's
+ * descriptor tables and reserve workspace on the calling thread's current
+ * stream: 1 GiB for gemm() and 768 MiB for gemm_scaled() (environment
+ * MGEMM_WORKSPACE_BYTES / MGEMM_SCALED_WORKSPACE_BYTES override the sizes;
+ * 0 reserves none).  Call it before any graph capture.  gemm() also works
+ * without it (no workspace: the configurations that need none run).
  */
 int gemm_init(const char *tune_table_path);
+/* Frees everything the library allocated on every device.  Call it only
+ * when no work that uses library memory is in flight. */
 void gemm_shutdown(void);
+
+/*
+ * Reserve workspace for the calling thread's current stream on the current
+ * device: at least `bytes` for gemm()'s packed split and split-K
+ * configurations and `scaled_bytes` for gemm_scaled() (0 leaves a
+ * reservation as it is; reservations only grow).  This call allocates
+ * (outside any graph capture: during one it returns GEMM_E_WORKSPACE); a
+ * replaced, smaller buffer is kept until gemm_shutdown or
+ * gemm_release_workspace, since work enqueued on the stream may still read
+ * it.  Errors: -1 / -2 for a negative size, GEMM_E_HIP when the allocation
+ * fails.  A reservation belongs to the stream handle: release it (or finish
+ * the stream's work) before destroying the stream.
+ */
+int gemm_reserve_workspace(int64_t bytes, int64_t scaled_bytes);
+
+/* Synchronises the calling thread's current stream and frees its
+ * reservations (and the buffers they replaced). */
+int gemm_release_workspace(void);
+
+/* Workspace bytes the configuration gemm() picks for these sizes (16-byte
+ * aligned operands) needs on the current device; 0 when it needs none, -1 for
+ * invalid arguments. */
+int64_t gemm_workspace_bytes(char transA, char transB, int64_t m, int64_t n, int64_t k, int dtype);
 
 /* Text of an error code (static storage). */
 const char *gemm_strerror(int code);
@@ -251,13 +290,21 @@ int gemm_last_config(int64_t out[4]);
  * Autotuner (paper section 8.4, "In search of the best micro-kernel": a
  * search over micro-kernel shapes of a few dozen experiments).  For every
  * (m, n, k) in `shapes` (3*count int64) it times each compiled configuration
- * of `dtype` (both raster orders) on library-allocated scratch operands,
- * keeps the fastest by median of `reps` launches, stores it under the
- * shape's size bucket for trans ('N','N') and writes the table as JSON to
- * `out_path` (NULL: keep in memory only).  Synchronous; allocates.
+ * of `dtype` that has a kernel for the layout (both raster orders) on
+ * library-allocated scratch operands, in each of the four layouts
+ * ('N','N', 'N','T', 'T','N', 'T','T'), keeps the fastest by median of `reps`
+ * launches, stores it under (layout, size bucket) and writes the table as
+ * JSON to `out_path` (NULL: keep in memory only).  Synchronous; allocates
+ * (its scratch operands and the workspace of its candidates, on a private
+ * stream, all freed before it returns).
  */
 int gemm_tune(int dtype, int64_t count, const int64_t *shapes, int reps,
               const char *out_path);
+
+/* gemm_tune_pruned restricted to the layouts whose bit is set in trans_mask
+ * (bit t = 2*(transA is 'T') + (transB is 'T'), 1..15; else -7). */
+int gemm_tune_layouts(int dtype, int64_t count, const int64_t *shapes, int reps,
+                      const char *out_path, int model_keep, int trans_mask);
 
 /*
  * gemm_tune restricted to the model_keep configurations the analytical model

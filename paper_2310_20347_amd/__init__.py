@@ -12,6 +12,6 @@ from ._binding import (  # noqa: F401
     force_config,
     gemm, gemm_scaled, gemm_grouped, gemm_grouped_capacity, gemm_init, gemm_shutdown, gemm_tune,
     GroupedSlot, PackedProblems, last_config, lib, lib_path, model_us, num_configs,
-    panel_occupancy,
-    set_stream, strerror,
+    panel_occupancy, release_workspace, reserve_workspace, scaled_workspace_bytes,
+    set_stream, strerror, workspace_bytes,
 )

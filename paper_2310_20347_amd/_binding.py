@@ -108,9 +108,20 @@ def lib():
     L.gemm_tune.argtypes = [_INT, _I64, ctypes.POINTER(_I64), _INT, ctypes.c_char_p]
     L.gemm_tune_pruned.argtypes = [_INT, _I64, ctypes.POINTER(_I64), _INT, ctypes.c_char_p, _INT]
     L.gemm_tune_pruned.restype = _INT
+    L.gemm_tune_layouts.argtypes = [_INT, _I64, ctypes.POINTER(_I64), _INT, ctypes.c_char_p, _INT,
+                                    _INT]
+    L.gemm_tune_layouts.restype = _INT
     L.gemm_model_us.argtypes = [_INT, _INT, _I64, _I64, _I64, _INT]
     L.gemm_model_us.restype = ctypes.c_double
     L.gemm_tune.restype = _INT
+    L.gemm_reserve_workspace.argtypes = [_I64, _I64]
+    L.gemm_reserve_workspace.restype = _INT
+    L.gemm_release_workspace.argtypes = []
+    L.gemm_release_workspace.restype = _INT
+    L.gemm_workspace_bytes.argtypes = [_C, _C, _I64, _I64, _I64, _INT]
+    L.gemm_workspace_bytes.restype = _I64
+    L.gemm_scaled_workspace_bytes.argtypes = [_C, _C, _I64, _I64, _I64, _D, _INT]
+    L.gemm_scaled_workspace_bytes.restype = _I64
     L.gemm_panel_occupancy.argtypes = [_I64, _I64, _I64, _I64]
     L.gemm_panel_occupancy.restype = _D
     _lib = L
@@ -261,6 +272,30 @@ def gemm_shutdown() -> None:
     lib().gemm_shutdown()
 
 
+def reserve_workspace(nbytes: int, scaled_bytes: int = 0, stream: Any = None) -> None:
+    """Reserve workspace for the current (or given) stream: `nbytes` for gemm()'s
+    packed split / split-K configurations, `scaled_bytes` for gemm_scaled()."""
+    set_stream(stream)
+    _check(lib().gemm_reserve_workspace(int(nbytes), int(scaled_bytes)), "gemm_reserve_workspace")
+
+
+def release_workspace(stream: Any = None) -> None:
+    """Synchronise the current (or given) stream and free its reservations."""
+    set_stream(stream)
+    _check(lib().gemm_release_workspace(), "gemm_release_workspace")
+
+
+def workspace_bytes(transA: str, transB: str, m: int, n: int, k: int, dtype: int) -> int:
+    """Workspace bytes the configuration gemm() picks for these sizes needs."""
+    return int(lib().gemm_workspace_bytes(_tc(transA), _tc(transB), m, n, k, int(dtype)))
+
+
+def scaled_workspace_bytes(transA: str, transB: str, m: int, n: int, k: int, beta: float,
+                           dtype: int) -> int:
+    return int(lib().gemm_scaled_workspace_bytes(_tc(transA), _tc(transB), m, n, k, float(beta),
+                                                 int(dtype)))
+
+
 def num_configs(dtype: int) -> int:
     return int(lib().gemm_num_configs(int(dtype)))
 
@@ -294,13 +329,17 @@ def last_config() -> dict:
 
 
 def gemm_tune(dtype: int, shapes: Sequence[Sequence[int]], reps: int = 10,
-              out_path: Optional[str] = None, model_keep: int = 0) -> None:
-    """Times the configurations on each shape (only the model's first
-    model_keep when > 0) and stores the fastest per size bucket."""
+              out_path: Optional[str] = None, model_keep: int = 0,
+              layouts: Sequence[str] = ("NN", "NT", "TN", "TT")) -> None:
+    """Times the configurations on each shape in each layout (only the model's
+    first model_keep when > 0) and stores the fastest per (layout, size bucket)."""
     flat = (_I64 * max(1, 3 * len(shapes)))(*[int(v) for s in shapes for v in s])
     p = out_path.encode() if out_path else None
-    _check(lib().gemm_tune_pruned(int(dtype), len(shapes), flat, int(reps), p, int(model_keep)),
-           "gemm_tune")
+    mask = 0
+    for lay in layouts:
+        mask |= 1 << (2 * (lay[0] in "TtCc") + (lay[1] in "TtCc"))
+    _check(lib().gemm_tune_layouts(int(dtype), len(shapes), flat, int(reps), p, int(model_keep),
+                                   mask), "gemm_tune")
 
 
 def model_us(dtype: int, cfg: int, m: int, n: int, k: int, cus: int = 256) -> float:

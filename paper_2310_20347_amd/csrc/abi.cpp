@@ -86,6 +86,9 @@ static bool int32_exact(double v)
     return std::isfinite(v) && v == std::floor(v) && v >= -2147483648.0 && v <= 2147483647.0;
 }
 
+// Arguments are checked in their order, so the code names the first invalid
+// one; checks that need the element size (operand alignment) are skipped
+// while the dtype (argument 14) is unknown, which is then reported last.
 int validate(char ta, char tb, int64_t m, int64_t n, int64_t k, double alpha, const void *A,
              int64_t lda, const void *B, int64_t ldb, double beta, const void *C, int64_t ldc,
              int dtype)
@@ -95,10 +98,10 @@ int validate(char ta, char tb, int64_t m, int64_t n, int64_t k, double alpha, co
     if (m < 0) return -3;
     if (n < 0) return -4;
     if (k < 0) return -5;
-    if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -14;
+    const bool dtype_ok = dtype >= 0 && dtype < GEMM_NUM_DTYPES;
     const bool is_int = dtype == GEMM_I8;
     if (is_int && !int32_exact(alpha)) return -6;
-    const int es = elem_bytes(kclass_of(dtype, k));
+    const int es = dtype_ok ? elem_bytes(kclass_of(dtype, k)) : 1;
     const bool form = m > 0 && n > 0 && k > 0 && alpha != 0.0;
     if (form && A == nullptr) return -7;
     if (A != nullptr && (reinterpret_cast<uintptr_t>(A) % es) != 0) return -7;
@@ -109,8 +112,10 @@ int validate(char ta, char tb, int64_t m, int64_t n, int64_t k, double alpha, co
     if (is_int && !int32_exact(beta)) return -11;
     const bool write = m > 0 && n > 0 && !((alpha == 0.0 || k == 0) && beta == 1.0);
     if (write && C == nullptr) return -12;
-    if (C != nullptr && (reinterpret_cast<uintptr_t>(C) % (dtype == GEMM_F64 ? 8 : 4)) != 0) return -12;
+    const int ces = !dtype_ok ? 1 : (dtype == GEMM_F64 ? 8 : 4);
+    if (C != nullptr && (reinterpret_cast<uintptr_t>(C) % ces) != 0) return -12;
     if (ldc < std::max<int64_t>(1, n)) return -13;
+    if (!dtype_ok) return -14;
     return 0;
 }
 
@@ -325,6 +330,12 @@ static void rebuild_lut_locked()
                         for (auto &kv : g_table) {
                             const TuneKey &t = kv.first;
                             if (t.kclass != kc) continue;
+                            // an entry tuned for another layout only counts
+                            // when its configuration has a kernel for this one
+                            if (t.trans != tr && kv.second.cfg >= 0 &&
+                                kv.second.cfg < (int)g_by_class[kc].size() &&
+                                !g_cfgs[g_by_class[kc][kv.second.cfg]].func[tr][1])
+                                continue;
                             const double d = std::abs(t.bm - bm) + std::abs(t.bn - bn) +
                                              std::abs(t.bk - bk) + (t.trans == tr ? 0.0 : 0.5);
                             if (d < best) {
@@ -356,9 +367,8 @@ static void ensure_table()
     if (probe) load_table(def.c_str());
 }
 
-// Default choice without a table entry: the tile that minimises a crude
-// cost = waves of workgroups x per-tile work (mc*nc) + panel traffic (mc+nc).
-// No tuned entry: the configuration the analytical model ranks first.
+// No tuned entry near the size bucket: the configuration the analytical
+// model ranks first among those built for the layout.
 static void heuristic(int kclass, int trans, int64_t m, int64_t n, int64_t k, int cus, int &id,
                       int &order, int &group)
 {
@@ -392,36 +402,62 @@ void select_config(int kclass, int trans, int64_t m, int64_t n, int64_t k, int c
     heuristic(kclass, trans, m, n, k, cus, id, order, group);
 }
 
-// Grow-only workspace of stream s on device d (NULL when it cannot be had).
+// Reserved workspace of stream s on device d, or NULL when the reservation
+// is smaller than `bytes`.  Never allocates, frees or synchronises.
 void *stream_workspace(DevState *d, hipStream_t s, size_t bytes, int slot)
 {
     std::lock_guard<std::mutex> g(d->ws_mu);
+    auto it = d->ws.find({s, slot});
+    if (it == d->ws.end() || it->second.second < bytes) return nullptr;
+    return it->second.first;
+}
+
+int reserve_workspace(DevState *d, hipStream_t s, size_t bytes, int slot)
+{
+    std::lock_guard<std::mutex> g(d->ws_mu);
     std::pair<void *, size_t> &w = d->ws[{s, slot}];
-    if (w.second >= bytes) return w.first;
-    // never allocate, free or synchronise inside a graph capture: the caller
-    // then runs a configuration that needs no workspace
+    if (w.second >= bytes) return GEMM_OK;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) {
         (void)hipGetLastError();
-        return nullptr;
+        return GEMM_E_WORKSPACE;
     }
-    if (w.first) {
-        // earlier GEMMs on this stream may still read the old buffer
-        (void)hipStreamSynchronize(s);
-        (void)hipFree(w.first);
-        w = {nullptr, 0};
-    }
-    const size_t gran = size_t(64) << 20;
+    const size_t gran = size_t(2) << 20;
     const size_t want = (bytes + gran - 1) / gran * gran;
     void *p = nullptr;
     const hipError_t e = hipMalloc(&p, want);
     if (e != hipSuccess) {
         t_tls.hip_err = (int)e;
         (void)hipGetLastError();
-        return nullptr;
+        return GEMM_E_HIP;
     }
+    // work already enqueued (or being enqueued by another thread) may still
+    // read the old buffer: keep it until shutdown / release
+    if (w.first) d->retired.push_back({{s, slot}, w.first});
     w = {p, want};
-    return p;
+    return GEMM_OK;
+}
+
+void release_workspaces(DevState *d, hipStream_t s)
+{
+    std::lock_guard<std::mutex> g(d->ws_mu);
+    (void)hipStreamSynchronize(s);
+    for (auto it = d->ws.begin(); it != d->ws.end();) {
+        if (it->first.first == s) {
+            if (it->second.first) (void)hipFree(it->second.first);
+            it = d->ws.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    for (auto it = d->retired.begin(); it != d->retired.end();) {
+        if (it->first.first == s) {
+            (void)hipFree(it->second);
+            it = d->retired.erase(it);
+        } else {
+            ++it;
+        }
+    }
 }
 
 void free_workspaces(DevState *d)
@@ -430,6 +466,57 @@ void free_workspaces(DevState *d)
     for (auto &kv : d->ws)
         if (kv.second.first) (void)hipFree(kv.second.first);
     d->ws.clear();
+    for (auto &r : d->retired) (void)hipFree(r.second);
+    d->retired.clear();
+}
+
+// Split-K plan: S slices of k (each a whole number of stages, at least two)
+// chosen to give about two workgroups per CU; S <= 1 runs the plain tile.
+static void splitk_plan(const KernelCfg &c, const GemmArgs &a, int cus, int64_t &S, int64_t &kslice)
+{
+    const int64_t tiles = int64_t(a.tiles_m) * a.tiles_n;
+    const int64_t nk = (int64_t(a.k) + c.kc - 1) / c.kc;
+    S = (2 * int64_t(cus) + tiles - 1) / tiles;
+    S = std::min<int64_t>(S, std::min<int64_t>(16, nk / 2));
+    kslice = 0;
+    if (S <= 1) return;
+    kslice = (nk + S - 1) / S * c.kc;
+    S = (a.k + kslice - 1) / kslice;
+}
+
+static void packed_sizes(const GemmArgs &a, int64_t &kp, size_t &abytes, size_t &bbytes)
+{
+    kp = packed_k(a.k, a.terms);
+    abytes = (size_t(a.m) * kp * 2 + 255) / 256 * 256;
+    bbytes = size_t(a.n) * kp * 2;
+}
+
+size_t workspace_need(const KernelCfg &c, const GemmArgs &a, int cus)
+{
+    if (c.packed >= 0) {
+        int64_t kp;
+        size_t ab, bb;
+        packed_sizes(a, kp, ab, bb);
+        return ab + bb;
+    }
+    if (c.base >= 0) {
+        int64_t S, kslice;
+        splitk_plan(c, a, cus, S, kslice);
+        return S > 1 ? size_t(S) * a.m * a.n * 4 : 0;
+    }
+    return 0;
+}
+
+int no_workspace_id(int kclass, int reg, bool vec)
+{
+    const KernelCfg &c = g_cfgs[reg];
+    if (c.packed >= 0) return vec ? 1 : 0;   // the fused split tile
+    if (c.base >= 0) {
+        const std::vector<int> &ids = g_by_class[kclass];
+        for (size_t i = 0; i < ids.size(); ++i)
+            if (ids[i] == c.base) return (int)i;   // the unsliced tile
+    }
+    return 0;
 }
 
 // Packed split product: pack op(A) and op(B) into k-contiguous bf16 pieces
@@ -438,10 +525,10 @@ void free_workspaces(DevState *d)
 static int launch_packed(const KernelCfg &c, int trans, const GemmArgs &a, hipStream_t s)
 {
     const int terms = a.terms;
-    const int64_t kp = packed_k(a.k, terms);
+    int64_t kp;
+    size_t abytes, bbytes;
+    packed_sizes(a, kp, abytes, bbytes);
     if (kp > 0x7FFFFFFF || terms <= 0) return kPackUnavailable;
-    const size_t abytes = (size_t(a.m) * kp * 2 + 255) / 256 * 256;
-    const size_t bbytes = size_t(a.n) * kp * 2;
     DevState *d = nullptr;
     int rc = device_state(&d);
     if (rc != GEMM_OK) return rc;
@@ -463,24 +550,19 @@ static int launch_packed(const KernelCfg &c, int trans, const GemmArgs &a, hipSt
     return launch_gemm(g_cfgs[c.packed], 1, true, b, s);
 }
 
-// Split-K: S slices of k (each a whole number of stages, at least two)
-// chosen to give about two workgroups per CU, partial tiles in the stream's
-// workspace, then the ordered reduction.  One slice runs the plain tile.
+// Split-K: partial tiles in the stream's workspace, then the ordered
+// reduction.  Without the workspace (or with one slice) the plain tile runs.
 static int launch_splitk(const KernelCfg &c, int trans, bool vec, const GemmArgs &a, hipStream_t s)
 {
     DevState *d = nullptr;
     int rc = device_state(&d);
     if (rc != GEMM_OK) return rc;
-    const int64_t tiles = int64_t(a.tiles_m) * a.tiles_n;
-    const int64_t nk = (int64_t(a.k) + c.kc - 1) / c.kc;
-    int64_t S = (2 * int64_t(d->cus) + tiles - 1) / tiles;
-    S = std::min<int64_t>(S, std::min<int64_t>(16, nk / 2));
+    int64_t S, kslice;
+    splitk_plan(c, a, d->cus, S, kslice);
     const KernelCfg &b = g_cfgs[c.base];
     if (S <= 1) return launch_gemm(b, trans, vec, a, s);
-    const int64_t kslice = (nk + S - 1) / S * c.kc;
-    S = (a.k + kslice - 1) / kslice;
-    const size_t bytes = size_t(S) * a.m * a.n * 4;
-    void *ws = stream_workspace(d, s, bytes);
+    const int64_t tiles = int64_t(a.tiles_m) * a.tiles_n;
+    void *ws = stream_workspace(d, s, size_t(S) * a.m * a.n * 4);
     if (!ws) return launch_gemm(b, trans, vec, a, s);
     const void *f = c.func[trans][vec ? 1 : 0];
     if (!f) return GEMM_E_UNSUPPORTED;
@@ -536,10 +618,18 @@ int plan_gemm(int dtype, char ta, char tb, int64_t m, int64_t n, int64_t k, doub
     vec = vec_ok(A, lda, es) && vec_ok(B, ldb, es);
     int reg = g_by_class[kclass][cfg_id];
     if (!g_cfgs[reg].func[trans][vec ? 1 : 0]) {
-        // the element-wise staging variant lives in the class's first configuration
-        cfg_id = 0;
-        reg = g_by_class[kclass][0];
-        if (!g_cfgs[reg].func[trans][vec ? 1 : 0]) return -1;
+        // no kernel of this configuration for the layout / staging: a tuned
+        // choice gives way to the model's best among the configurations that
+        // have one; a forced one to the class's first configuration, which
+        // carries every element-wise staging variant
+        const bool forced = t_tls.force_id[kclass] >= 0;
+        cfg_id = forced ? 0 : model_best(kclass, trans, vec, m, n, k, cus);
+        reg = g_by_class[kclass][cfg_id];
+        if (!g_cfgs[reg].func[trans][vec ? 1 : 0]) {
+            cfg_id = 0;
+            reg = g_by_class[kclass][0];
+            if (!g_cfgs[reg].func[trans][vec ? 1 : 0]) return -1;
+        }
     }
     const KernelCfg &c = g_cfgs[reg];
     a.A = A;
@@ -603,16 +693,20 @@ int gemm(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha
     const int reg = plan_gemm(dtype, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
                               d->cus, a, trans, vec, cfg, kclass);
     if (reg < 0) return GEMM_E_UNSUPPORTED;
-    rc = launch_gemm(g_cfgs[reg], trans, vec, a, s);
-    if (rc == kPackUnavailable) {
-        // no workspace for the packed split: the fused split tile instead
+    int run = reg;
+    const size_t need = workspace_need(g_cfgs[reg], a, d->cus);
+    if (need > 0 && !stream_workspace(d, s, need, 0)) {
+        // the stream's reserved workspace is too small (nothing is allocated
+        // here): the class's configuration that needs none
         const int saved = t_tls.force_id[kclass];
-        t_tls.force_id[kclass] = vec ? 1 : 0;
-        const int reg2 = plan_gemm(dtype, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta,
-                                   C, ldc, d->cus, a, trans, vec, cfg, kclass);
+        t_tls.force_id[kclass] = no_workspace_id(kclass, reg, vec);
+        run = plan_gemm(dtype, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                        d->cus, a, trans, vec, cfg, kclass);
         t_tls.force_id[kclass] = saved;
-        rc = reg2 < 0 ? GEMM_E_UNSUPPORTED : launch_gemm(g_cfgs[reg2], trans, vec, a, s);
+        if (run < 0) return GEMM_E_UNSUPPORTED;
     }
+    rc = launch_gemm(g_cfgs[run], trans, vec, a, s);
+    if (rc == kPackUnavailable) rc = GEMM_E_UNSUPPORTED;   // packing pass not built for this case
     if (rc == GEMM_OK) {
         t_tls.last[0] = dtype;
         t_tls.last[1] = cfg;
@@ -628,6 +722,23 @@ int gemm_set_stream(void *hip_stream)
     return GEMM_OK;
 }
 
+// Default reservations of gemm_init on the calling thread's stream (bytes;
+// MGEMM_WORKSPACE_BYTES / MGEMM_SCALED_WORKSPACE_BYTES override, 0 = none):
+// enough for the packed split product at 8192^3 (2 (m + n) 3k bf16 values,
+// 805 MB) and for the scaled path's quantised operands and partial product
+// at 8192^3 in binary16 with beta != 0 (about 537 MB).
+constexpr int64_t kDefaultWorkspace = int64_t(1) << 30;
+constexpr int64_t kDefaultScaledWorkspace = int64_t(768) << 20;
+
+static int64_t env_bytes(const char *name, int64_t dflt)
+{
+    const char *v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    char *end = nullptr;
+    const long long x = std::strtoll(v, &end, 10);
+    return (end && *end == '\0' && x >= 0) ? (int64_t)x : dflt;
+}
+
 int gemm_init(const char *tune_table_path)
 {
     ensure_registered();
@@ -636,10 +747,18 @@ int gemm_init(const char *tune_table_path)
     if (rc != GEMM_OK) return rc;
     if (tune_table_path && *tune_table_path) {
         g_table_loaded = true;
-        return load_table(tune_table_path);
+        rc = load_table(tune_table_path);
+        if (rc != GEMM_OK) return rc;
+    } else {
+        ensure_table();
     }
-    ensure_table();
-    return grouped_device_init(d);
+    rc = grouped_device_init(d);
+    if (rc != GEMM_OK) return rc;
+    const hipStream_t s = t_tls.stream;
+    rc = reserve_workspace(d, s, (size_t)env_bytes("MGEMM_WORKSPACE_BYTES", kDefaultWorkspace), 0);
+    if (rc != GEMM_OK) return rc;
+    return reserve_workspace(d, s,
+                             (size_t)env_bytes("MGEMM_SCALED_WORKSPACE_BYTES", kDefaultScaledWorkspace), 1);
 }
 
 void gemm_shutdown(void)
@@ -648,6 +767,54 @@ void gemm_shutdown(void)
         grouped_device_free(&g_dev[i]);
         free_workspaces(&g_dev[i]);
     }
+}
+
+int gemm_reserve_workspace(int64_t bytes, int64_t scaled_bytes)
+{
+    if (bytes < 0) return -1;
+    if (scaled_bytes < 0) return -2;
+    DevState *d = nullptr;
+    int rc = device_state(&d);
+    if (rc != GEMM_OK) return rc;
+    const hipStream_t s = t_tls.stream;
+    if (bytes > 0 && (rc = reserve_workspace(d, s, (size_t)bytes, 0)) != GEMM_OK) return rc;
+    if (scaled_bytes > 0 && (rc = reserve_workspace(d, s, (size_t)scaled_bytes, 1)) != GEMM_OK)
+        return rc;
+    return GEMM_OK;
+}
+
+int gemm_release_workspace(void)
+{
+    DevState *d = nullptr;
+    int rc = device_state(&d);
+    if (rc != GEMM_OK) return rc;
+    release_workspaces(d, t_tls.stream);
+    return GEMM_OK;
+}
+
+int64_t gemm_workspace_bytes(char transA, char transB, int64_t m, int64_t n, int64_t k, int dtype)
+{
+    if (dtype < 0 || dtype >= GEMM_NUM_DTYPES || !trans_ok(transA) || !trans_ok(transB) || m < 0 ||
+        n < 0 || k < 0)
+        return -1;
+    if (m == 0 || n == 0 || k == 0) return 0;
+    if (m > 0x7FFFFFFF || n > 0x7FFFFFFF || k > 0x7FFFFFFF) return -1;
+    ensure_registered();
+    DevState *d = nullptr;
+    if (device_state(&d) != GEMM_OK) return -1;
+    // 16-byte aligned stand-in operands with the smallest leading dimensions
+    const int es = elem_bytes(kclass_of(dtype, k));
+    const int64_t lda = is_trans(transA) ? m : k, ldb = is_trans(transB) ? k : n;
+    const int64_t al = 16 / es;
+    const void *fake = (const void *)uintptr_t(4096);
+    GemmArgs a;
+    int trans = 0, cfg = 0, kclass = 0;
+    bool vec = true;
+    const int reg = plan_gemm(dtype, transA, transB, m, n, k, 1.0, fake, (lda + al - 1) / al * al,
+                              fake, (ldb + al - 1) / al * al, 0.0, (void *)fake, n, d->cus, a, trans,
+                              vec, cfg, kclass);
+    if (reg < 0) return 0;
+    return (int64_t)workspace_need(g_cfgs[reg], a, d->cus);
 }
 
 const char *gemm_strerror(int code)

@@ -23,10 +23,15 @@ struct DevState {
     // grouped launches: device descriptor tables and pinned host staging
     bool grouped_ready = false;
     void *grouped = nullptr;
-    // packed split operands: one grow-only workspace per stream (work on one
-    // stream is ordered, so its GEMMs can share it)
+    // workspaces reserved per stream (work on one stream is ordered, so its
+    // GEMMs can share one); only gemm_init, gemm_reserve_workspace and the
+    // tuner allocate them, GEMM calls only look them up
     std::mutex ws_mu;
     std::map<std::pair<hipStream_t, int>, std::pair<void *, size_t>> ws;   // (stream, slot)
+    // buffers replaced by a larger reservation: a call on another thread may
+    // still be enqueuing work that reads them, so they are freed only at
+    // gemm_shutdown (or gemm_release_workspace of their stream)
+    std::vector<std::pair<std::pair<hipStream_t, int>, void *>> retired;
 };
 
 // Internal status of launch_gemm: a packed configuration could not get its
@@ -94,8 +99,21 @@ int launch_split_pack(const float *X, int64_t ld, bool kmode, int64_t rows, int6
                       bool a_side, unsigned short *out, hipStream_t s);
 const void *split_pack_entry();
 // slot 0: the kernels' own workspace (packed split, split-K); slot 1: the
-// scaled path's quantised operands, which outlive the GEMM it calls
+// scaled path's quantised operands, which outlive the GEMM it calls.
+// stream_workspace returns the stream's reserved buffer when it holds at
+// least `bytes`, else NULL; it never allocates, frees or synchronises.
 void *stream_workspace(DevState *d, hipStream_t s, size_t bytes, int slot = 0);
+// Grows the reservation of (s, slot) to at least `bytes` (allocates; refused
+// during a graph capture).  The replaced buffer is retired, not freed.
+int reserve_workspace(DevState *d, hipStream_t s, size_t bytes, int slot);
+// Frees every reservation of stream s (and its retired buffers) after
+// synchronising the stream.
+void release_workspaces(DevState *d, hipStream_t s);
+// Workspace bytes configuration c needs for the planned call a (0: none).
+size_t workspace_need(const KernelCfg &c, const GemmArgs &a, int cus);
+// Configuration of the same class that needs no workspace, for c (id within
+// the class), when c's workspace is not available.
+int no_workspace_id(int kclass, int reg, bool vec);
 
 // Analytical model (model.cpp): cycles / microseconds of configuration c on
 // an m x n x k problem, and the class's configuration it ranks first.

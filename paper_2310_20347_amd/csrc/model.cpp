@@ -137,7 +137,7 @@ int model_best(int kclass, int trans, bool vec, int64_t m, int64_t n, int64_t k,
     double best_t = 1e300;
     for (size_t i = 0; i < ids.size(); ++i) {
         const KernelCfg &c = g_cfgs[ids[i]];
-        if (!c.func[trans][vec ? 1 : 0] && c.packed < 0 && c.base < 0) continue;
+        if (!c.func[trans][vec ? 1 : 0]) continue;
         const double t = model_cycles(c, kclass, m, n, k, cus);
         if (t < best_t * 0.999) {
             best_t = t;

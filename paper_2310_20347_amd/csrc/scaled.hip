@@ -202,62 +202,86 @@ void launch_exponents(bool contig, const float *X, int64_t ld, int R, int K, int
     hipLaunchKernelGGL(col_exponents, dim3(gx), dim3(256), 0, s, part, R, T, e);
 }
 
-}  // namespace
-}  // namespace mg
+// Workspace layout of one scaled call: exponents e (m) and f (n), partial
+// maxima of the strided exponent reductions, the quantised operands, and the
+// FP32 partial product when beta != 0 (else the product goes to C).
+struct ScaledLayout {
+    int fmt, T, es;
+    bool ta, tb;
+    int64_t ar, ac, br, bc, ldqa, ldqb;
+    int64_t e_bytes, f_bytes, part_bytes, qa_bytes, qb_bytes, p_bytes;
+    int64_t total() const { return e_bytes + f_bytes + part_bytes + qa_bytes + qb_bytes + p_bytes; }
+};
 
-using namespace mg;
-
-extern "C" int gemm_scaled(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha,
-                           const void *A, int64_t lda, const void *B, int64_t ldb, double beta, void *C,
-                           int64_t ldc, int dtype)
+ScaledLayout scaled_layout(char transA, char transB, int64_t m, int64_t n, int64_t k, double beta,
+                           int dtype)
 {
-    if (dtype != GEMM_BF16 && dtype != GEMM_F16 && dtype != GEMM_F8E4M3) return -14;
-    // FP32 operands and C: the FP32 rules of gemm()
+    ScaledLayout L;
+    L.ta = is_trans(transA);
+    L.tb = is_trans(transB);
+    L.fmt = dtype == GEMM_BF16 ? 0 : (dtype == GEMM_F16 ? 1 : 2);
+    L.T = L.fmt == 0 ? kT_BF16 : (L.fmt == 1 ? kT_F16 : kT_E4M3);
+    L.es = L.fmt == 2 ? 1 : 2;
+    // stored shapes: A is m x k ('N') or k x m ('T'); B is k x n ('N') or n x k ('T')
+    L.ar = L.ta ? k : m;
+    L.ac = L.ta ? m : k;
+    L.br = L.tb ? n : k;
+    L.bc = L.tb ? k : n;
+    L.ldqa = round_up(L.ac, 16 / L.es);
+    L.ldqb = round_up(L.bc, 16 / L.es);
+    L.e_bytes = round_up(m * 4, 256);
+    L.f_bytes = round_up(n * 4, 256);
+    L.part_bytes = L.e_bytes + L.f_bytes;
+    L.qa_bytes = round_up(L.ar * L.ldqa * L.es, 256);
+    L.qb_bytes = round_up(L.br * L.ldqb * L.es, 256);
+    L.p_bytes = beta != 0.0 ? m * n * 4 : 0;
+    return L;
+}
+
+// Common argument checks and quick returns of the scaled entry points:
+// 1 = proceed, otherwise the return code.
+int scaled_check(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha,
+                 const void *A, int64_t lda, const void *B, int64_t ldb, double beta, void *C,
+                 int64_t ldc, int dtype)
+{
+    // FP32 operands and C: the FP32 rules of gemm(), then the format (argument 14)
     const int v = validate(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, GEMM_F32);
     if (v != 0) return v;
+    if (dtype != GEMM_BF16 && dtype != GEMM_F16 && dtype != GEMM_F8E4M3) return -14;
     if (m == 0 || n == 0) return GEMM_OK;
-    if (alpha == 0.0 || k == 0) return gemm(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, GEMM_F32);
+    if (alpha == 0.0 || k == 0)
+        return gemm(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, GEMM_F32);
     if (m > 0x7FFFFFFF || n > 0x7FFFFFFF || k > 0x7FFFFFFF) return GEMM_E_UNSUPPORTED;
-    ensure_registered();
-    DevState *d = nullptr;
-    int rc = device_state(&d);
-    if (rc != GEMM_OK) return rc;
-    hipStream_t s = t_tls.stream;
-    const bool ta = is_trans(transA), tb = is_trans(transB);
-    const int fmt = dtype == GEMM_BF16 ? 0 : (dtype == GEMM_F16 ? 1 : 2);
-    const int T = fmt == 0 ? kT_BF16 : (fmt == 1 ? kT_F16 : kT_E4M3);
-    const int es = fmt == 2 ? 1 : 2;
-    // stored shapes: A is m x k ('N') or k x m ('T'); B is k x n ('N') or n x k ('T')
-    const int64_t ar = ta ? k : m, ac = ta ? m : k, br = tb ? n : k, bc = tb ? k : n;
-    const int64_t ldqa = round_up(ac, 16 / es), ldqb = round_up(bc, 16 / es);
-    const int64_t e_bytes = round_up(m * 4, 256), f_bytes = round_up(n * 4, 256);
-    const int64_t part_bytes = e_bytes + f_bytes;   // partial maxima of strided reductions
-    const int64_t qa_bytes = round_up(ar * ldqa * es, 256), qb_bytes = round_up(br * ldqb * es, 256);
-    const int64_t p_bytes = beta != 0.0 ? m * n * 4 : 0;
-    char *ws = (char *)stream_workspace(
-        d, s, (size_t)(e_bytes + f_bytes + part_bytes + qa_bytes + qb_bytes + p_bytes), 1);
-    if (!ws) return GEMM_E_WORKSPACE;
-    int *e = (int *)ws, *f = (int *)(ws + e_bytes);
-    u32 *part_a = (u32 *)(ws + e_bytes + f_bytes), *part_b = (u32 *)(ws + 2 * e_bytes + f_bytes);
-    char *qa = ws + e_bytes + f_bytes + part_bytes, *qb = qa + qa_bytes;
-    float *P = p_bytes ? (float *)(qb + qb_bytes) : (float *)C;
-    const int64_t ldp = p_bytes ? n : ldc;
+    return 1;
+}
+
+// The scaled product's passes on the workspace `ws` (L.total() bytes).
+int scaled_run(const ScaledLayout &L, char transA, char transB, int64_t m, int64_t n, int64_t k,
+               double alpha, const void *A, int64_t lda, const void *B, int64_t ldb, double beta,
+               void *C, int64_t ldc, int dtype, char *ws, hipStream_t s)
+{
+    int *e = (int *)ws, *f = (int *)(ws + L.e_bytes);
+    u32 *part_a = (u32 *)(ws + L.e_bytes + L.f_bytes), *part_b = (u32 *)(ws + 2 * L.e_bytes + L.f_bytes);
+    char *qa = ws + L.e_bytes + L.f_bytes + L.part_bytes, *qb = qa + L.qa_bytes;
+    float *P = L.p_bytes ? (float *)(qb + L.qb_bytes) : (float *)C;
+    const int64_t ldp = L.p_bytes ? n : ldc;
+    const bool ta = L.ta, tb = L.tb;
     // op(A) row i: stored row i ('N', contiguous) or stored column i ('T');
     // op(B) column j: stored column j ('N') or stored row j ('T', contiguous)
-    launch_exponents(!ta, (const float *)A, lda, (int)m, (int)k, T, e, part_a, s);
-    launch_exponents(tb, (const float *)B, ldb, (int)n, (int)k, T, f, part_b, s);
-    switch (fmt) {
+    launch_exponents(!ta, (const float *)A, lda, (int)m, (int)k, L.T, e, part_a, s);
+    launch_exponents(tb, (const float *)B, ldb, (int)n, (int)k, L.T, f, part_b, s);
+    switch (L.fmt) {
     case 0:
-        launch_quantize<0>(!ta, (const float *)A, lda, (int)ar, (int)ac, e, qa, ldqa, s);
-        launch_quantize<0>(tb, (const float *)B, ldb, (int)br, (int)bc, f, qb, ldqb, s);
+        launch_quantize<0>(!ta, (const float *)A, lda, (int)L.ar, (int)L.ac, e, qa, L.ldqa, s);
+        launch_quantize<0>(tb, (const float *)B, ldb, (int)L.br, (int)L.bc, f, qb, L.ldqb, s);
         break;
     case 1:
-        launch_quantize<1>(!ta, (const float *)A, lda, (int)ar, (int)ac, e, qa, ldqa, s);
-        launch_quantize<1>(tb, (const float *)B, ldb, (int)br, (int)bc, f, qb, ldqb, s);
+        launch_quantize<1>(!ta, (const float *)A, lda, (int)L.ar, (int)L.ac, e, qa, L.ldqa, s);
+        launch_quantize<1>(tb, (const float *)B, ldb, (int)L.br, (int)L.bc, f, qb, L.ldqb, s);
         break;
     default:
-        launch_quantize<2>(!ta, (const float *)A, lda, (int)ar, (int)ac, e, qa, ldqa, s);
-        launch_quantize<2>(tb, (const float *)B, ldb, (int)br, (int)bc, f, qb, ldqb, s);
+        launch_quantize<2>(!ta, (const float *)A, lda, (int)L.ar, (int)L.ac, e, qa, L.ldqa, s);
+        launch_quantize<2>(tb, (const float *)B, ldb, (int)L.br, (int)L.bc, f, qb, L.ldqb, s);
         break;
     }
     hipError_t err = hipGetLastError();
@@ -265,7 +289,7 @@ extern "C" int gemm_scaled(char transA, char transB, int64_t m, int64_t n, int64
         t_tls.hip_err = (int)err;
         return GEMM_E_HIP;
     }
-    rc = gemm(transA, transB, m, n, k, 1.0, qa, ldqa, qb, ldqb, 0.0, P, ldp, dtype);
+    const int rc = gemm(transA, transB, m, n, k, 1.0, qa, L.ldqa, qb, L.ldqb, 0.0, P, ldp, dtype);
     if (rc != GEMM_OK) return rc;
     hipLaunchKernelGGL(scale_epilogue, grid2(m, n), dim3(256), 0, s, (const float *)P, ldp,
                        (float *)C, ldc, (int)m, (int)n, e, f, (float)alpha, (float)beta);
@@ -275,4 +299,36 @@ extern "C" int gemm_scaled(char transA, char transB, int64_t m, int64_t n, int64
         return GEMM_E_HIP;
     }
     return GEMM_OK;
+}
+
+}  // namespace
+}  // namespace mg
+
+using namespace mg;
+
+extern "C" int gemm_scaled(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha,
+                           const void *A, int64_t lda, const void *B, int64_t ldb, double beta, void *C,
+                           int64_t ldc, int dtype)
+{
+    const int c = scaled_check(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype);
+    if (c != 1) return c;
+    ensure_registered();
+    DevState *d = nullptr;
+    int rc = device_state(&d);
+    if (rc != GEMM_OK) return rc;
+    hipStream_t s = t_tls.stream;
+    const ScaledLayout L = scaled_layout(transA, transB, m, n, k, beta, dtype);
+    // the stream's reserved workspace (gemm_init / gemm_reserve_workspace)
+    char *ws = (char *)stream_workspace(d, s, (size_t)L.total(), 1);
+    if (!ws) return GEMM_E_WORKSPACE;
+    return scaled_run(L, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype, ws, s);
+}
+
+extern "C" int64_t gemm_scaled_workspace_bytes(char transA, char transB, int64_t m, int64_t n,
+                                               int64_t k, double beta, int dtype)
+{
+    if (dtype != GEMM_BF16 && dtype != GEMM_F16 && dtype != GEMM_F8E4M3) return -1;
+    if (m < 0 || n < 0 || k < 0) return -1;
+    if (m == 0 || n == 0 || k == 0) return 0;
+    return scaled_layout(transA, transB, m, n, k, beta, dtype).total();
 }

@@ -4,7 +4,7 @@
 // compiled tile configurations x raster order (B3A2C0 / A3B2C0) x raster
 // group, with analytical pruning (the role the paper gives to the cache
 // model of section 8.2): configurations whose kernels use scratch (spills;
-// section 8.7 shows a spilling micro-kernel losing half its speed) are
+// section 8.10 shows a spilling micro-kernel losing half its speed) are
 // rejected, and so are configurations whose staged panels do not fit LDS.
 // A second phase re-times the few fastest candidates of each shape in
 // interleaved rounds: the MFMA-dense kernels run under a power limit whose
@@ -44,14 +44,15 @@ extern "C" double gemm_panel_occupancy(int64_t rows, int64_t cols, int64_t elem_
     return double(rows) * double(cols) * double(elem_bytes) / double(capacity_bytes);
 }
 
-extern "C" int gemm_tune_pruned(int dtype, int64_t count, const int64_t *shapes, int reps,
-                                const char *out_path, int model_keep)
+extern "C" int gemm_tune_layouts(int dtype, int64_t count, const int64_t *shapes, int reps,
+                                 const char *out_path, int model_keep, int trans_mask)
 {
     if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -1;
     if (count < 0) return -2;
     if (count > 0 && !shapes) return -3;
     if (reps < 1) return -4;
     if (model_keep < 0) return -6;
+    if (trans_mask < 1 || trans_mask > 15) return -7;
     ensure_registered();
     DevState *d = nullptr;
     int rc = device_state(&d);
@@ -73,6 +74,7 @@ extern "C" int gemm_tune_pruned(int dtype, int64_t count, const int64_t *shapes,
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto fail = [&](hipError_t e) {
         t_tls.hip_err = (int)e;
+        if (s) release_workspaces(d, s);
         if (A) (void)hipFree(A);
         if (B) (void)hipFree(B);
         if (C) (void)hipFree(C);
@@ -89,10 +91,21 @@ extern "C" int gemm_tune_pruned(int dtype, int64_t count, const int64_t *shapes,
     if ((e = hipEventCreate(&e0)) != hipSuccess) return fail(e);
     if ((e = hipEventCreate(&e1)) != hipSuccess) return fail(e);
 
+    // the tuner's private stream gets the workspace its candidates need
+    // (tuning allocates; the reservation is released at the end)
+    auto reserve_for = [&](const KernelCfg &c, const GemmArgs &a) -> bool {
+        const size_t need = workspace_need(c, a, d->cus);
+        return need == 0 || reserve_workspace(d, s, need, 0) == GEMM_OK;
+    };
     static const int kGroups[3] = {4, 8, 16};
-    for (int64_t i = 0; i < count; ++i) {
+    for (int64_t i = 0; i < count; ++i)
+    for (int tr = 0; tr < 4; ++tr) {
+        if (!((trans_mask >> tr) & 1)) continue;
         const int64_t m = shapes[3 * i], n = shapes[3 * i + 1], k = shapes[3 * i + 2];
         const int kclass = kclass_of(dtype, k);
+        // layout tr = 2*(A is 'T') + (B is 'T'): A stored m x k or k x m, B k x n or n x k
+        const char ta = (tr >> 1) ? 'T' : 'N', tb = (tr & 1) ? 'T' : 'N';
+        const int64_t lda = (tr >> 1) ? m : k, ldb = (tr & 1) ? k : n;
         launch_fill(A, m * k, fill_kind(kclass), 1u, s);
         launch_fill(B, k * n, fill_kind(kclass), 2u, s);
         struct Cand {
@@ -116,9 +129,9 @@ extern "C" int gemm_tune_pruned(int dtype, int64_t count, const int64_t *shapes,
         }
         for (size_t id = 0; id < ids.size(); ++id) {
             const KernelCfg &c = g_cfgs[ids[id]];
-            if (!c.func[0][1] || !keep[id]) continue;
+            if (!c.func[tr][1] || !keep[id]) continue;
             hipFuncAttributes attr;
-            if (hipFuncGetAttributes(&attr, c.func[0][1]) == hipSuccess && attr.localSizeBytes > 0)
+            if (hipFuncGetAttributes(&attr, c.func[tr][1]) == hipSuccess && attr.localSizeBytes > 0)
                 continue;   // spills: rejected
             if (gemm_panel_occupancy(1, c.lds, 1, 160 * 1024) > 1.0)
                 continue;   // staged panels exceed one CU's LDS
@@ -132,12 +145,12 @@ extern "C" int gemm_tune_pruned(int dtype, int64_t count, const int64_t *shapes,
                     t_tls.force_id[kclass] = (int)id;
                     t_tls.force_order[kclass] = order;
                     t_tls.force_group = kGroups[gi];
-                    const int reg = plan_gemm(dtype, 'N', 'N', m, n, k, 1.0, A, k, B, n, 0.0, C, n,
+                    const int reg = plan_gemm(dtype, ta, tb, m, n, k, 1.0, A, lda, B, ldb, 0.0, C, n,
                                               d->cus, a, trans, vec, cfg, kc2);
                     t_tls.force_id[kclass] = saved;
                     t_tls.force_order[kclass] = saved_o;
                     t_tls.force_group = 0;
-                    if (reg < 0 || cfg != (int)id) continue;
+                    if (reg < 0 || cfg != (int)id || !reserve_for(g_cfgs[reg], a)) continue;
                     std::vector<float> ms;
                     for (int r = 0; r < reps + 2; ++r) {
                         (void)hipEventRecord(e0, s);
@@ -196,9 +209,10 @@ extern "C" int gemm_tune_pruned(int dtype, int64_t count, const int64_t *shapes,
         }
         {
             std::lock_guard<std::mutex> g(g_mu);
-            g_table[TuneKey{kclass, 0, bucket(m), bucket(n), bucket(k)}] = best;
+            g_table[TuneKey{kclass, tr, bucket(m), bucket(n), bucket(k)}] = best;
         }
     }
+    release_workspaces(d, s);
     (void)hipFree(A);
     (void)hipFree(B);
     (void)hipFree(C);
@@ -210,7 +224,13 @@ extern "C" int gemm_tune_pruned(int dtype, int64_t count, const int64_t *shapes,
     return GEMM_OK;
 }
 
+extern "C" int gemm_tune_pruned(int dtype, int64_t count, const int64_t *shapes, int reps,
+                                const char *out_path, int model_keep)
+{
+    return gemm_tune_layouts(dtype, count, shapes, reps, out_path, model_keep, 15);
+}
+
 extern "C" int gemm_tune(int dtype, int64_t count, const int64_t *shapes, int reps, const char *out_path)
 {
-    return gemm_tune_pruned(dtype, count, shapes, reps, out_path, 0);
+    return gemm_tune_layouts(dtype, count, shapes, reps, out_path, 0, 15);
 }

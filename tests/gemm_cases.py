@@ -86,8 +86,21 @@ def decode(stored_arr, dtype):
     return stored_arr.astype(np.float64)
 
 
+_INITIALISED = False
+
+
+def gpu_init():
+    """gemm_init once per process: the tuning table, the grouped tables and
+    the default workspace reservations of the current stream."""
+    global _INITIALISED
+    if not _INITIALISED:
+        mg.gemm_init(None)
+        _INITIALISED = True
+
+
 def to_device(arr):
     import torch
+    gpu_init()
     a = np.ascontiguousarray(arr)
     if a.dtype == np.uint16:
         a = a.view(np.int16)

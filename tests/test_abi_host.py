@@ -55,6 +55,31 @@ def test_invalid_arguments_report_their_position(kw, code):
 def test_first_invalid_argument_wins():
     assert call(ta="X", m=-1, ldc=0) == -1
     assert call(m=-1, ldc=0) == -3
+    # the dtype is argument 14: a bad lda (8) or C (12) together with a bad dtype reports 8 / 12
+    assert call(lda=2, dtype=99) == -8
+    assert call(C=None, dtype=-1) == -12
+    assert call(ldc=4, dtype=99) == -13
+    # an operand misaligned for some element size is not judged while the dtype is unknown
+    assert call(A=0x1001, dtype=99) == -14
+
+
+def test_workspace_entry_points_validate_on_the_host():
+    L = mg.lib()
+    assert L.gemm_reserve_workspace(-1, 0) == -1
+    assert L.gemm_reserve_workspace(0, -5) == -2
+    assert L.gemm_workspace_bytes(b"X", b"N", 4, 4, 4, mg.GEMM_F32) == -1
+    assert L.gemm_workspace_bytes(b"N", b"N", 4, 4, 4, 99) == -1
+    assert L.gemm_workspace_bytes(b"N", b"N", -1, 4, 4, mg.GEMM_F32) == -1
+    assert L.gemm_workspace_bytes(b"N", b"N", 0, 4, 4, mg.GEMM_F32) == 0
+    assert mg.scaled_workspace_bytes("N", "N", 4, 4, 4, 0.0, mg.GEMM_F32) == -1
+    # exponents (256-byte rounded) x 2, partial maxima x 2, quantised A and B, no P at beta 0
+    m, n, k = 100, 60, 36
+    qa = -(-(m * 40 * 2) // 256) * 256   # rows of k rounded up to 8 binary16 values
+    qb = -(-(k * 64 * 2) // 256) * 256   # rows of n rounded up to 8 values
+    e, f = 512, 256
+    assert mg.scaled_workspace_bytes("N", "N", m, n, k, 0.0, mg.GEMM_F16) == 2 * (e + f) + qa + qb
+    assert (mg.scaled_workspace_bytes("N", "N", m, n, k, 1.0, mg.GEMM_F16)
+            == 2 * (e + f) + qa + qb + 4 * m * n)
 
 
 def test_transposed_leading_dimensions():
@@ -133,7 +158,10 @@ def test_gemm_scaled_validates_before_touching_the_device():
     # only the narrow formats; FP32 argument rules; quick return for m == 0
     L = mg.lib()
     n_, p_ = b"N", 0x1000
-    assert L.gemm_scaled(n_, n_, 4, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, mg.GEMM_F32) == -14
+    assert L.gemm_scaled(n_, n_, 4, 4, 4, 1.0, p_, 4, p_, 4, 0.0, p_, 4, mg.GEMM_F32) == -14
+    # arguments are checked in order: a missing A (7) is reported before the format (14)
+    assert L.gemm_scaled(n_, n_, 4, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, mg.GEMM_F32) == -7
+    assert L.gemm_scaled(n_, n_, 4, 4, 4, 1.0, p_, 2, p_, 4, 0.0, p_, 4, 99) == -8
     assert L.gemm_scaled(n_, n_, 4, 4, 4, 1.0, p_, 2, p_, 4, 0.0, p_, 4, mg.GEMM_F16) == -8
     assert L.gemm_scaled(b"X", n_, 4, 4, 4, 1.0, p_, 4, p_, 4, 0.0, p_, 4, mg.GEMM_F8E4M3) == -1
     assert L.gemm_scaled(n_, n_, 0, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, mg.GEMM_BF16) == 0

@@ -193,11 +193,11 @@ def test_split_k_configurations_vs_oracle(dtype, ta, tb):
                          ids=["f32-splitk", "bf16x3-packed", "bf16x3-splitk"])
 def test_workspace_configurations_under_graph_capture(dtype, kind):
     """Configurations that use the per-stream workspace (packed split, split-K)
-    inside a captured HIP graph.  With the workspace grown before capture the
-    replays reproduce the eager result bit for bit (each replay checked, with
-    eager work in between); on a stream that has none the capture takes a
-    configuration that needs no workspace, allocating nothing, and the replay
-    still matches the oracle."""
+    inside a captured HIP graph.  With the workspace reserved before capture
+    the replays reproduce the eager result bit for bit (each replay checked,
+    with eager work in between); on a stream that has none the capture takes
+    a configuration that needs no workspace, allocating nothing, and the
+    replay still matches the oracle."""
     import torch
     from gemm_cases import stored
     cfg = [i for i in range(mg.num_configs(dtype)) if mg.config_info(dtype, i)["kind"] == kind][0]
@@ -212,8 +212,12 @@ def test_workspace_configurations_under_graph_capture(dtype, kind):
     try:
         mg.force_config(dtype, cfg, 0)
         s1 = torch.cuda.Stream()
+        need = mg.workspace_bytes("N", "N", m, n, k, dtype)
+        assert need > 0
+        mg.reserve_workspace(need, 0, stream=s1)
         mg.gemm("N", "N", m, n, k, 1.0, dA, k, dB, n, 0.0, dC, n, dtype, stream=s1)
         torch.cuda.synchronize()
+        assert mg.last_config()["cfg"] == cfg
         eager = dC.cpu().numpy().copy()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.stream(s1):
@@ -230,6 +234,7 @@ def test_workspace_configurations_under_graph_capture(dtype, kind):
         with torch.cuda.stream(s2):
             with torch.cuda.graph(g2, stream=s2):
                 mg.gemm("N", "N", m, n, k, 1.0, dA, k, dB, n, 0.0, dC, n, dtype, stream=s2)
+        assert mg.last_config()["cfg"] != cfg   # the configuration without workspace
         dC.fill_(7.0)
         torch.cuda.synchronize()
         g2.replay()
@@ -237,6 +242,8 @@ def test_workspace_configurations_under_graph_capture(dtype, kind):
         err = oracle.normalized_error(dC.cpu().numpy(), ref_q, k, float(np.abs(a32).max()),
                                       float(np.abs(b32).max()))
         assert err <= 2e-6, f"fallback capture error {err:.3g}"
+        del g, g2
+        mg.release_workspace(stream=s1)
     finally:
         mg.force_config(dtype, -1, 0)
 
