@@ -12,6 +12,8 @@ Every routine is a thin ctypes wrapper over ``oracle_gemm.c``:
                     summed as the plain i -> p -> j triple loop of section 5.1.
 * ``gemm_i8``       the same over int8 inputs with exact int64 sums, wrapped to
                     int32 at the end.
+* ``gemm_int``      int16 or int32 inputs: the exact integer value of
+                    alpha*op(A)*op(B) + beta*C0 modulo 2^32 (int32 C).
 * ``gemm_pieces``   the split-product form used by the FP32-accurate path:
                     op(A) = sum of bf16 pieces, only listed piece pairs formed.
 * ``entries_*``     individual entries C(i, j) of the same definitions, for
@@ -66,6 +68,10 @@ def _load():
                                    _I64, _P, _I64, _P, _I64]
     lib.oracle_gemm_entries_i8.argtypes = [_C, _C, _I64, _I64, _P, _I64, _P, _I64, _I64,
                                            _P, _I64, _I64, _P, _P, _P]
+    lib.oracle_gemm_int.argtypes = [_INT, _C, _C, _I64, _I64, _I64, _I64, _P, _I64, _P, _I64,
+                                    _I64, _P, _I64, _P, _I64]
+    lib.oracle_gemm_entries_int.argtypes = [_INT, _C, _C, _I64, _I64, _P, _I64, _P, _I64, _I64,
+                                            _P, _I64, _I64, _P, _P, _P]
     lib.oracle_decode_bf16.argtypes = [_P, _I64, _P]
     lib.oracle_decode_f16.argtypes = [_P, _I64, _P]
     lib.oracle_decode_e4m3.argtypes = [_P, _I64, _P]
@@ -73,7 +79,8 @@ def _load():
     lib.oracle_scale_exponents.argtypes = [_P, _I64, _I64, _INT, _P]
     lib.oracle_scaled_codes.argtypes = [_P, _I64, _I64, _P, _INT, _P]
     for f in ("oracle_gemm_f64", "oracle_gemm_entries_f64", "oracle_gemm_pieces_f64",
-              "oracle_gemm_i8", "oracle_gemm_entries_i8", "oracle_decode_bf16",
+              "oracle_gemm_i8", "oracle_gemm_entries_i8", "oracle_gemm_int",
+              "oracle_gemm_entries_int", "oracle_decode_bf16",
               "oracle_decode_f16", "oracle_decode_e4m3", "oracle_split_bf16",
               "oracle_scale_exponents", "oracle_scaled_codes"):
         getattr(lib, f).restype = None
@@ -202,6 +209,58 @@ def gemm_i8(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta=0, C0=None, ldc0=None):
         lib.oracle_gemm_i8(_tc(ta), _tc(tb), m, n, k, int(alpha), _ptr(A), lda,
                            _ptr(B), ldb, int(beta), _ptr(C0f), ldc0, _ptr(C), n)
     return C
+
+
+def _int_kind(bits):
+    if bits == 16:
+        return 2, np.int16
+    if bits == 32:
+        return 4, np.int32
+    raise ValueError("bits must be 16 or 32")
+
+
+def _int32_scalar(v, name):
+    if int(v) != v or not -2**31 <= int(v) < 2**31:
+        raise ValueError(f"{name} must be an int32 integer")
+    return int(v)
+
+
+def gemm_int(bits, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta=0, C0=None, ldc0=None):
+    """INT16 / INT32 definition: the exact integer alpha*op(A)*op(B) + beta*C0
+    modulo 2^32, as int32 (A, B int16 when bits == 16, int32 when 32)."""
+    lib = _load()
+    eb, dt = _int_kind(bits)
+    alpha = _int32_scalar(alpha, "alpha")
+    beta = _int32_scalar(beta, "beta")
+    A = _flat(A, dt)
+    B = _flat(B, dt)
+    ldc0 = n if ldc0 is None else ldc0
+    C0f = _flat(C0, np.int32) if (C0 is not None and beta != 0) else np.zeros(0, np.int32)
+    _check_ld(ta, tb, m, n, k, lda, ldb, ldc0, A, B, C0f, beta)
+    C = np.empty((m, n), dtype=np.int32)
+    if m and n:
+        lib.oracle_gemm_int(eb, _tc(ta), _tc(tb), m, n, k, alpha, _ptr(A), lda, _ptr(B), ldb,
+                            beta, _ptr(C0f), ldc0, _ptr(C), n)
+    return C
+
+
+def entries_int(bits, ta, tb, k, alpha, A, lda, B, ldb, beta, C0, ldc0, rows, cols):
+    """C(rows[t], cols[t]) of the INT16 / INT32 definition."""
+    lib = _load()
+    eb, dt = _int_kind(bits)
+    alpha = _int32_scalar(alpha, "alpha")
+    beta = _int32_scalar(beta, "beta")
+    A = _flat(A, dt)
+    B = _flat(B, dt)
+    rows = _flat(rows, np.int64)
+    cols = _flat(cols, np.int64)
+    C0f = _flat(C0, np.int32) if (C0 is not None and beta != 0) else np.zeros(0, np.int32)
+    out = np.empty(rows.size, dtype=np.int32)
+    if rows.size:
+        lib.oracle_gemm_entries_int(eb, _tc(ta), _tc(tb), k, alpha, _ptr(A), lda, _ptr(B), ldb,
+                                    beta, _ptr(C0f), ldc0, rows.size, _ptr(rows), _ptr(cols),
+                                    _ptr(out))
+    return out
 
 
 def entries_i8(ta, tb, k, alpha, A, lda, B, ldb, beta, C0, ldc0, rows, cols):

@@ -15,7 +15,8 @@
  * op(A)(i,p) * op(B)(p,j): the paper's basic triple loop (section 5.1,
  * "Basic GEMM with TVM") in the i -> p -> j nesting, with no blocking.
  * Floating point is FP64; INT8 accumulates exactly in int64 and wraps the
- * final value to int32 (two's complement).
+ * final value to int32 (two's complement); INT16 and INT32 keep the exact
+ * value modulo 2^32 (int32 C).
  *
  * BLAS conventions (the paper defines only C += AB):
  *   alpha == 0 or k == 0 : the product is not formed and A, B are not read;
@@ -217,6 +218,85 @@ void oracle_gemm_entries_i8(char ta, char tb, int64_t k, int64_t alpha,
         out[t] = wrap32((int64_t)v);
     }
 }
+
+/* ---------------------------------------------------------------------- */
+/* INT16 and INT32 GEMM (the paper's 16- and 32-bit integer routines of its */
+/* data-type study, section 8.5).  A and B hold int16 (ebytes 2) or int32   */
+/* (ebytes 4) values; C0 and C are int32.  The result is the exact integer  */
+/* alpha * sum_p op(A)(i,p) op(B)(p,j) + beta * C0(i,j) reduced modulo 2^32 */
+/* (two's complement).  It is computed in unsigned 64-bit arithmetic, which */
+/* wraps modulo 2^64 and so keeps the low 32 bits of every product and sum  */
+/* exact.  alpha and beta are int32 values.                                  */
+/* ---------------------------------------------------------------------- */
+static int64_t int_at(const void *X, int ebytes, int64_t idx)
+{
+    if (ebytes == 2) return ((const int16_t *)X)[idx];
+    return ((const int32_t *)X)[idx];
+}
+
+static int32_t low32(uint64_t v)
+{
+    uint32_t u = (uint32_t)(v & 0xFFFFFFFFull);
+    int32_t r;
+    memcpy(&r, &u, sizeof r);
+    return r;
+}
+
+void oracle_gemm_int(int ebytes, char ta, char tb, int64_t m, int64_t n, int64_t k,
+                     int64_t alpha, const void *A, int64_t lda,
+                     const void *B, int64_t ldb, int64_t beta,
+                     const int32_t *C0, int64_t ldc0, int32_t *C, int64_t ldc)
+{
+    const int at = is_t(ta), bt = is_t(tb);
+    const int form = (alpha != 0) && (k > 0);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < m; ++i) {
+        uint64_t acc[CHUNK];
+        for (int64_t j0 = 0; j0 < n; j0 += CHUNK) {
+            const int64_t jn = (n - j0 < CHUNK) ? n - j0 : CHUNK;
+            for (int64_t j = 0; j < jn; ++j) acc[j] = 0u;
+            if (form) {
+                for (int64_t p = 0; p < k; ++p) {
+                    const uint64_t a = (uint64_t)int_at(A, ebytes, at ? p * lda + i : i * lda + p);
+                    for (int64_t j = 0; j < jn; ++j) {
+                        const uint64_t b =
+                            (uint64_t)int_at(B, ebytes, bt ? (j0 + j) * ldb + p : p * ldb + (j0 + j));
+                        acc[j] += a * b;
+                    }
+                }
+            }
+            for (int64_t j = 0; j < jn; ++j) {
+                uint64_t v = form ? (uint64_t)alpha * acc[j] : 0u;
+                if (beta != 0) v += (uint64_t)beta * (uint64_t)(int64_t)C0[i * ldc0 + (j0 + j)];
+                C[i * ldc + (j0 + j)] = low32(v);
+            }
+        }
+    }
+}
+
+/* Selected entries of the same definition: out[t] = C(rows[t], cols[t]). */
+void oracle_gemm_entries_int(int ebytes, char ta, char tb, int64_t k, int64_t alpha,
+                             const void *A, int64_t lda, const void *B, int64_t ldb,
+                             int64_t beta, const int32_t *C0, int64_t ldc0,
+                             int64_t count, const int64_t *rows, const int64_t *cols,
+                             int32_t *out)
+{
+    const int at = is_t(ta), bt = is_t(tb);
+    const int form = (alpha != 0) && (k > 0);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < count; ++t) {
+        const int64_t i = rows[t], j = cols[t];
+        uint64_t s = 0u;
+        if (form)
+            for (int64_t p = 0; p < k; ++p)
+                s += (uint64_t)int_at(A, ebytes, at ? p * lda + i : i * lda + p) *
+                     (uint64_t)int_at(B, ebytes, bt ? j * ldb + p : p * ldb + j);
+        uint64_t v = form ? (uint64_t)alpha * s : 0u;
+        if (beta != 0) v += (uint64_t)beta * (uint64_t)(int64_t)C0[i * ldc0 + j];
+        out[t] = low32(v);
+    }
+}
+
 
 /* ---------------------------------------------------------------------- */
 /* Number formats.                                                          */

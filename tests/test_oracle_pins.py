@@ -441,3 +441,182 @@ def test_gemm_scaled_reference_equals_definition():
     Ct = oracle.gemm_scaled("T", "T", m, n, k, 1.5, a.T.copy(), m, b.T.copy(), k, "f16",
                             -0.5, c0, n)[0]
     assert np.array_equal(C, Ct)
+
+
+# -- INT16 / INT32: exact integer value modulo 2^32 ------------------------------------
+
+INT_DT = {16: np.int16, 32: np.int32}
+
+
+def _int_operand(rng, shape, bits, extremes=True):
+    lo, hi = -2 ** (bits - 1), 2 ** (bits - 1)
+    x = rng.integers(lo, hi, size=shape, dtype=np.int64)
+    if extremes and x.size >= 4:
+        flat = x.reshape(-1)
+        flat[0], flat[1], flat[-1] = lo, hi - 1, lo   # the most negative, most positive values
+    return x.astype(INT_DT[bits])
+
+
+def _run_int(g, bits, ta, tb, alpha, opA, opB, beta=0, C0=None, pad=0):
+    m, k = opA.shape
+    n = opB.shape[1]
+    As, Bs = stored(opA, ta), stored(opB, tb)
+    if pad:
+        As = np.pad(As, ((0, 0), (0, pad)), constant_values=-1)
+        Bs = np.pad(Bs, ((0, 0), (0, pad)), constant_values=-1)
+    return g(bits, ta, tb, m, n, k, alpha, As, As.shape[1], Bs, Bs.shape[1], beta, C0, n)
+
+
+def _wrap32_py(v):
+    v &= 0xFFFFFFFF
+    return v - (1 << 32) if v >= 1 << 31 else v
+
+
+def pin_int_python_bigints(g):
+    """Brute force in Python's exact integers on small inputs with extreme values."""
+    rng = np.random.default_rng(61)
+    for bits in (16, 32):
+        for ta, tb in TRANS:
+            m, n, k = 3, 4, 5
+            A = _int_operand(rng, (m, k), bits)
+            B = _int_operand(rng, (k, n), bits)
+            C0 = rng.integers(-2**31, 2**31, size=(m, n), dtype=np.int64).astype(np.int32)
+            alpha, beta = int(rng.integers(-2**31, 2**31)), int(rng.integers(-2**31, 2**31))
+            C = _run_int(g, bits, ta, tb, alpha, A, B, beta, C0, pad=2)
+            for i in range(m):
+                for j in range(n):
+                    s = sum(int(A[i, p]) * int(B[p, j]) for p in range(k))
+                    if C[i, j] != _wrap32_py(alpha * s + beta * int(C0[i, j])):
+                        return False
+    return True
+
+
+def pin_int_numpy(g):
+    """int16: numpy's int64 matmul is exact; int32: numpy's uint64 matmul wraps
+    modulo 2^64, which keeps the low 32 bits exact."""
+    rng = np.random.default_rng(62)
+    m, n, k = 13, 11, 67
+    for ta, tb in TRANS:
+        A = _int_operand(rng, (m, k), 16)
+        B = _int_operand(rng, (k, n), 16)
+        ref = (A.astype(np.int64) @ B.astype(np.int64)) * 3
+        if not np.array_equal(_run_int(g, 16, ta, tb, 3, A, B, pad=1), ref.astype(np.int32)):
+            return False
+        A = _int_operand(rng, (m, k), 32)
+        B = _int_operand(rng, (k, n), 32)
+        ref = (A.astype(np.int64).astype(np.uint64) @ B.astype(np.int64).astype(np.uint64))
+        ref = (ref * np.uint64(2**32 - 7)) & np.uint64(0xFFFFFFFF)   # alpha = -7 modulo 2^32
+        if not np.array_equal(_run_int(g, 32, ta, tb, -7, A, B, pad=1),
+                              ref.astype(np.uint32).view(np.int32)):
+            return False
+    return True
+
+
+def pin_int_closed_forms(g):
+    """All -32768 (int16): C = k 2^30 modulo 2^32; identity: C = op(B) exactly;
+    rank one with u_i = 2^16 + i, v_j = 2^16 - j: C = k u_i v_j modulo 2^32."""
+    for k, want in ((1, 2**30), (2, -2**31), (3, -2**30), (4, 0), (5, 2**30)):
+        A = np.full((2, k), -32768, np.int16)
+        B = np.full((k, 3), -32768, np.int16)
+        if not np.all(_run_int(g, 16, "N", "N", 1, A, B) == want):
+            return False
+    rng = np.random.default_rng(63)
+    for ta, tb in TRANS:
+        Bm = _int_operand(rng, (6, 4), 32)
+        C = _run_int(g, 32, ta, tb, 1, np.eye(6, dtype=np.int32), Bm, pad=3)
+        if not np.array_equal(C, Bm):
+            return False
+    m, n, k = 4, 3, 9
+    u = np.array([2**16 + i for i in range(m)], np.int64)
+    v = np.array([2**16 - j for j in range(n)], np.int64)
+    A = np.repeat(u[:, None], k, axis=1).astype(np.int32)
+    B = np.repeat(v[None, :], k, axis=0).astype(np.int32)
+    C = _run_int(g, 32, "N", "N", 1, A, B)
+    want = [[_wrap32_py(k * int(u[i]) * int(v[j])) for j in range(n)] for i in range(m)]
+    return np.array_equal(C, np.array(want, np.int32))
+
+
+def pin_int_blas_special(g):
+    """alpha == 0 reads neither A nor B (C = beta C0); beta == 0 does not read C0;
+    k == 0 gives beta C0."""
+    rng = np.random.default_rng(64)
+    C0 = rng.integers(-2**31, 2**31, size=(3, 4), dtype=np.int64).astype(np.int32)
+    A = _int_operand(rng, (3, 5), 32)
+    B = _int_operand(rng, (5, 4), 32)
+    C = _run_int(g, 32, "N", "N", 0, A, B, 3, C0)
+    if not np.array_equal(C, (C0.astype(np.int64) * 3).astype(np.int32)):
+        return False
+    C = _run_int(g, 32, "N", "N", 1, A, B, 0, np.full((3, 4), 123456, np.int32))
+    ref = (A.astype(np.int64).astype(np.uint64) @ B.astype(np.int64).astype(np.uint64))
+    return np.array_equal(C, (ref & np.uint64(0xFFFFFFFF)).astype(np.uint32).view(np.int32))
+
+
+INT_PINS = [pin_int_python_bigints, pin_int_numpy, pin_int_closed_forms, pin_int_blas_special]
+
+
+@pytest.mark.parametrize("pin", INT_PINS, ids=lambda p: p.__name__)
+def test_int_oracle_passes_pin(pin):
+    assert pin(oracle.gemm_int)
+
+
+def _mut_int_drop_last_term(bits, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C0, ldc0):
+    return oracle.gemm_int(bits, ta, tb, m, n, max(k - 1, 0), alpha, A, lda, B, ldb, beta, C0,
+                           ldc0)
+
+
+def _mut_int_int32_accumulator(bits, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C0, ldc0):
+    # products kept in int32 before the sum: wrong whenever a product exceeds 2^31
+    A = np.asarray(A).reshape(-1).astype(np.int64)
+    B = np.asarray(B).reshape(-1).astype(np.int64)
+    opA = (A[:k * lda].reshape(k, lda)[:, :m].T if ta in "Tt" else A[:m * lda].reshape(m, lda)[:, :k])
+    opB = (B[:n * ldb].reshape(n, ldb)[:, :k].T if tb in "Tt" else B[:k * ldb].reshape(k, ldb)[:, :n])
+    prod = np.clip(opA[:, :, None] * opB[None, :, :], -2**31, 2**31 - 1).sum(axis=1)
+    v = alpha * prod
+    if beta != 0:
+        v = v + beta * np.asarray(C0, np.int64).reshape(m, -1)[:, :n]
+    return (v & 0xFFFFFFFF).astype(np.uint32).view(np.int32)
+
+
+def _mut_int_narrow_operand(bits, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C0, ldc0):
+    # 32-bit operands read through 16 bits
+    A = np.asarray(A).astype(np.int16) if bits == 32 else A
+    return oracle.gemm_int(bits, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C0, ldc0)
+
+
+def _mut_int_transposed(bits, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C0, ldc0):
+    ta2 = "N" if ta in "Tt" else "T"
+    try:
+        return oracle.gemm_int(bits, ta2, tb, m, n, k, alpha, A, lda, B, ldb, beta, C0, ldc0)
+    except ValueError:
+        return np.full((m, n), 0, np.int32)
+
+
+INT_MUTANTS = [_mut_int_drop_last_term, _mut_int_int32_accumulator, _mut_int_narrow_operand,
+               _mut_int_transposed]
+
+
+@pytest.mark.parametrize("mutant", INT_MUTANTS, ids=lambda f: f.__name__)
+def test_int_pins_catch_planted_mistake(mutant):
+    def safe(pin):
+        try:
+            return pin(mutant)
+        except (ValueError, IndexError):
+            return False
+    assert not all(safe(p) for p in INT_PINS), "no pin caught this planted mistake"
+
+
+def test_int_entries_equal_full_product():
+    rng = np.random.default_rng(65)
+    m, n, k = 17, 21, 45
+    for bits in (16, 32):
+        for ta, tb in TRANS:
+            A = stored(_int_operand(rng, (m, k), bits), ta)
+            B = stored(_int_operand(rng, (k, n), bits), tb)
+            C0 = rng.integers(-2**31, 2**31, size=(m, n), dtype=np.int64).astype(np.int32)
+            full = oracle.gemm_int(bits, ta, tb, m, n, k, -5, A, A.shape[1], B, B.shape[1], 7,
+                                   C0, n)
+            rows = rng.integers(0, m, 40)
+            cols = rng.integers(0, n, 40)
+            e = oracle.entries_int(bits, ta, tb, k, -5, A, A.shape[1], B, B.shape[1], 7, C0, n,
+                                   rows, cols)
+            assert np.array_equal(e, full[rows, cols])
