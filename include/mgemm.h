@@ -80,7 +80,8 @@ enum {
     GEMM_E_HIP = 1,          /* a HIP runtime call failed; see gemm_last_hip_error()      */
     GEMM_E_UNSUPPORTED = 2,  /* no kernel built for this dtype / configuration             */
     GEMM_E_NOINIT = 3,       /* no usable GPU device                                       */
-    GEMM_E_WORKSPACE = 4,    /* grouped problem count above the workspace capacity         */
+    GEMM_E_WORKSPACE = 4,    /* workspace too small: grouped count above capacity, or a    */
+                             /* configuration's workspace above what the call may use      */
     GEMM_E_TUNE_TABLE = 5,   /* tuning table file unreadable or malformed                  */
     GEMM_E_SERVE = 6         /* serving loop: invalid configuration or backend failure     */
 };
@@ -106,6 +107,33 @@ enum {
 int gemm(char transA, char transB, int64_t m, int64_t n, int64_t k,
          double alpha, const void *A, int64_t lda, const void *B, int64_t ldb,
          double beta, void *C, int64_t ldc, int dtype);
+
+/*
+ * gemm_noalloc: gemm() for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, layouts, semantics and results as gemm() (the
+ * same configuration is chosen, so results are bitwise equal to gemm()'s
+ * whenever gemm() has the workspace that configuration needs).  Packed split
+ * and split-K configurations take their workspace from a fixed device array
+ * of gemm_noalloc_scratch_bytes() = 64 MiB that the library holds on each
+ * GPU it runs on until the process ends; no reservation or gemm_init is
+ * needed (gemm_init looks the array up ahead of time; otherwise the first
+ * call on a device does).  The call never allocates, frees or synchronises.
+ * When the chosen configuration needs more than 64 MiB of workspace
+ * (gemm_workspace_bytes), the call returns GEMM_E_WORKSPACE and launches
+ * nothing: run gemm() instead.  All calls on one GPU share the array, and
+ * each call overwrites what the last left there: calls that may execute at
+ * the same time on one GPU (different streams without ordering between
+ * them) race; calls on one stream, or otherwise ordered, are safe.  Nothing
+ * in the array needs to start at zero (every byte a launch reads was written
+ * earlier in the same call).  Argument errors as gemm().
+ */
+int gemm_noalloc(char transA, char transB, int64_t m, int64_t n, int64_t k,
+                 double alpha, const void *A, int64_t lda, const void *B, int64_t ldb,
+                 double beta, void *C, int64_t ldc, int dtype);
+
+/* Size in bytes of gemm_noalloc's fixed device scratch array. */
+int64_t gemm_noalloc_scratch_bytes(void);
 
 /*
  * Power-of-two scaled low-precision GEMM on FP32 operands (A, B, C float32,

@@ -71,6 +71,11 @@ def lib():
     L.gemm_scaled.argtypes = [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64, _INT]
     L.gemm_scaled.restype = _INT
     L.gemm.restype = _INT
+    L.gemm_noalloc.argtypes = [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64,
+                               _INT]
+    L.gemm_noalloc.restype = _INT
+    L.gemm_noalloc_scratch_bytes.argtypes = []
+    L.gemm_noalloc_scratch_bytes.restype = _I64
     L.gemm_grouped.argtypes = [_I64, ctypes.POINTER(_Problem), _INT]
     L.gemm_grouped.restype = _INT
     L.gemm_grouped_capacity.argtypes = []
@@ -176,6 +181,23 @@ def gemm(transA: str, transB: str, m: int, n: int, k: int, alpha: float, A, lda:
     rc = lib().gemm(_tc(transA), _tc(transB), m, n, k, float(alpha), _ptr(A), lda, _ptr(B),
                     ldb, float(beta), _ptr(C), ldc, int(dtype))
     return _check(rc, "gemm") if check else rc
+
+
+def gemm_noalloc(transA: str, transB: str, m: int, n: int, k: int, alpha: float, A, lda: int, B,
+                 ldb: int, beta: float, C, ldc: int, dtype: int, stream: Any = None,
+                 check: bool = True) -> int:
+    """gemm() whose workspace configurations use the library's fixed device
+    scratch array: never allocates; GEMM_E_WORKSPACE when the chosen
+    configuration needs more than noalloc_scratch_bytes()."""
+    set_stream(stream)
+    rc = lib().gemm_noalloc(_tc(transA), _tc(transB), m, n, k, float(alpha), _ptr(A), lda,
+                            _ptr(B), ldb, float(beta), _ptr(C), ldc, int(dtype))
+    return _check(rc, "gemm_noalloc") if check else rc
+
+
+def noalloc_scratch_bytes() -> int:
+    """Size of gemm_noalloc's fixed device scratch array."""
+    return int(lib().gemm_noalloc_scratch_bytes())
 
 
 def gemm_scaled(transA: str, transB: str, m: int, n: int, k: int, alpha: float, A, lda: int, B,

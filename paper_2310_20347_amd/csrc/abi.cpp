@@ -412,6 +412,18 @@ void *stream_workspace(DevState *d, hipStream_t s, size_t bytes, int slot)
     return it->second.first;
 }
 
+Workspace stream_reservation(DevState *d, hipStream_t s, int slot)
+{
+    std::lock_guard<std::mutex> g(d->ws_mu);
+    auto it = d->ws.find({s, slot});
+    Workspace w;
+    if (it != d->ws.end()) {
+        w.ptr = it->second.first;
+        w.bytes = it->second.second;
+    }
+    return w;
+}
+
 int reserve_workspace(DevState *d, hipStream_t s, size_t bytes, int slot)
 {
     std::lock_guard<std::mutex> g(d->ws_mu);
@@ -520,23 +532,21 @@ int no_workspace_id(int kclass, int reg, bool vec)
 }
 
 // Packed split product: pack op(A) and op(B) into k-contiguous bf16 pieces
-// in the stream's workspace, then run the bf16 tile c.packed ('N','T') over
-// the packed k.
-static int launch_packed(const KernelCfg &c, int trans, const GemmArgs &a, hipStream_t s)
+// in the workspace w, then run the bf16 tile c.packed ('N','T') over the
+// packed k.
+static int launch_packed(const KernelCfg &c, int trans, const GemmArgs &a, hipStream_t s,
+                         Workspace w)
 {
     const int terms = a.terms;
     int64_t kp;
     size_t abytes, bbytes;
     packed_sizes(a, kp, abytes, bbytes);
     if (kp > 0x7FFFFFFF || terms <= 0) return kPackUnavailable;
-    DevState *d = nullptr;
-    int rc = device_state(&d);
-    if (rc != GEMM_OK) return rc;
-    char *ws = (char *)stream_workspace(d, s, abytes + bbytes);
-    if (!ws) return kPackUnavailable;
+    if (!w.ptr || w.bytes < abytes + bbytes) return kPackUnavailable;
+    char *ws = (char *)w.ptr;
     unsigned short *pa = (unsigned short *)ws, *pb = (unsigned short *)(ws + abytes);
     const bool ta = (trans >> 1) != 0, tb = (trans & 1) != 0;
-    rc = launch_split_pack((const float *)a.A, a.lda, !ta, a.m, a.k, terms, true, pa, s);
+    int rc = launch_split_pack((const float *)a.A, a.lda, !ta, a.m, a.k, terms, true, pa, s);
     if (rc == GEMM_E_UNSUPPORTED) return kPackUnavailable;
     if (rc != GEMM_OK) return rc;
     rc = launch_split_pack((const float *)a.B, a.ldb, tb, a.n, a.k, terms, false, pb, s);
@@ -550,9 +560,10 @@ static int launch_packed(const KernelCfg &c, int trans, const GemmArgs &a, hipSt
     return launch_gemm(g_cfgs[c.packed], 1, true, b, s);
 }
 
-// Split-K: partial tiles in the stream's workspace, then the ordered
-// reduction.  Without the workspace (or with one slice) the plain tile runs.
-static int launch_splitk(const KernelCfg &c, int trans, bool vec, const GemmArgs &a, hipStream_t s)
+// Split-K: partial tiles in the workspace w, then the ordered reduction.
+// Without enough workspace (or with one slice) the plain tile runs.
+static int launch_splitk(const KernelCfg &c, int trans, bool vec, const GemmArgs &a, hipStream_t s,
+                         Workspace w)
 {
     DevState *d = nullptr;
     int rc = device_state(&d);
@@ -562,8 +573,8 @@ static int launch_splitk(const KernelCfg &c, int trans, bool vec, const GemmArgs
     const KernelCfg &b = g_cfgs[c.base];
     if (S <= 1) return launch_gemm(b, trans, vec, a, s);
     const int64_t tiles = int64_t(a.tiles_m) * a.tiles_n;
-    void *ws = stream_workspace(d, s, size_t(S) * a.m * a.n * 4);
-    if (!ws) return launch_gemm(b, trans, vec, a, s);
+    if (!w.ptr || w.bytes < size_t(S) * a.m * a.n * 4) return launch_gemm(b, trans, vec, a, s);
+    void *ws = w.ptr;
     const void *f = c.func[trans][vec ? 1 : 0];
     if (!f) return GEMM_E_UNSUPPORTED;
     GemmArgs copy = a;
@@ -581,10 +592,11 @@ static int launch_splitk(const KernelCfg &c, int trans, bool vec, const GemmArgs
     return GEMM_OK;
 }
 
-int launch_gemm(const KernelCfg &c, int trans, bool vec, const GemmArgs &a, hipStream_t s)
+int launch_gemm(const KernelCfg &c, int trans, bool vec, const GemmArgs &a, hipStream_t s,
+                Workspace w)
 {
-    if (c.packed >= 0) return launch_packed(c, trans, a, s);
-    if (c.base >= 0) return launch_splitk(c, trans, vec, a, s);
+    if (c.packed >= 0) return launch_packed(c, trans, a, s, w);
+    if (c.base >= 0) return launch_splitk(c, trans, vec, a, s, w);
     const void *f = c.func[trans][vec ? 1 : 0];
     if (!f) return GEMM_E_UNSUPPORTED;
     const int64_t blocks = int64_t(a.tiles_m) * a.tiles_n;
@@ -655,14 +667,9 @@ int plan_gemm(int dtype, char ta, char tb, int64_t m, int64_t n, int64_t k, doub
     return reg;
 }
 
-}  // namespace mg
-
-using namespace mg;
-
-extern "C" {
-
-int gemm(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha, const void *A,
-         int64_t lda, const void *B, int64_t ldb, double beta, void *C, int64_t ldc, int dtype)
+int gemm_ws(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha,
+            const void *A, int64_t lda, const void *B, int64_t ldb, double beta, void *C,
+            int64_t ldc, int dtype, Workspace w, bool reject_short)
 {
     const int v = validate(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype);
     if (v != 0) return v;
@@ -695,9 +702,10 @@ int gemm(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha
     if (reg < 0) return GEMM_E_UNSUPPORTED;
     int run = reg;
     const size_t need = workspace_need(g_cfgs[reg], a, d->cus);
-    if (need > 0 && !stream_workspace(d, s, need, 0)) {
-        // the stream's reserved workspace is too small (nothing is allocated
-        // here): the class's configuration that needs none
+    if (need > 0 && (!w.ptr || w.bytes < need)) {
+        if (reject_short) return GEMM_E_WORKSPACE;
+        // the workspace is too small (nothing is allocated here): the
+        // class's configuration that needs none
         const int saved = t_tls.force_id[kclass];
         t_tls.force_id[kclass] = no_workspace_id(kclass, reg, vec);
         run = plan_gemm(dtype, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
@@ -705,7 +713,7 @@ int gemm(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha
         t_tls.force_id[kclass] = saved;
         if (run < 0) return GEMM_E_UNSUPPORTED;
     }
-    rc = launch_gemm(g_cfgs[run], trans, vec, a, s);
+    rc = launch_gemm(g_cfgs[run], trans, vec, a, s, w);
     if (rc == kPackUnavailable) rc = GEMM_E_UNSUPPORTED;   // packing pass not built for this case
     if (rc == GEMM_OK) {
         t_tls.last[0] = dtype;
@@ -714,6 +722,27 @@ int gemm(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha
         t_tls.last[3] = a.terms;
     }
     return rc;
+}
+
+}  // namespace mg
+
+using namespace mg;
+
+extern "C" {
+
+int gemm(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha, const void *A,
+         int64_t lda, const void *B, int64_t ldb, double beta, void *C, int64_t ldc, int dtype)
+{
+    // argument errors before any runtime call
+    const int v = validate(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype);
+    if (v != 0) return v;
+    // the workspace reserved for the calling thread's stream (none when the
+    // device has no state yet: gemm_ws reports that device's error itself)
+    Workspace w;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices && g_dev[dev].init)
+        w = stream_reservation(&g_dev[dev], t_tls.stream, 0);
+    return gemm_ws(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype, w, false);
 }
 
 int gemm_set_stream(void *hip_stream)
@@ -753,6 +782,8 @@ int gemm_init(const char *tune_table_path)
         ensure_table();
     }
     rc = grouped_device_init(d);
+    if (rc != GEMM_OK) return rc;
+    rc = scratch_device_init(d->device);
     if (rc != GEMM_OK) return rc;
     const hipStream_t s = t_tls.stream;
     rc = reserve_workspace(d, s, (size_t)env_bytes("MGEMM_WORKSPACE_BYTES", kDefaultWorkspace), 0);
@@ -825,7 +856,7 @@ const char *gemm_strerror(int code)
     case GEMM_E_HIP: return "HIP runtime error";
     case GEMM_E_UNSUPPORTED: return "unsupported dtype, size or configuration";
     case GEMM_E_NOINIT: return "no usable GPU device";
-    case GEMM_E_WORKSPACE: return "grouped problem count exceeds workspace capacity";
+    case GEMM_E_WORKSPACE: return "workspace too small (grouped problem count, or the workspace a configuration needs)";
     case GEMM_E_TUNE_TABLE: return "tuning table unreadable or malformed";
     case GEMM_E_SERVE: return "serving loop configuration or backend failure";
     default: return "unknown error";

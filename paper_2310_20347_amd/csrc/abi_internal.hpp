@@ -87,7 +87,25 @@ bool vec_ok(const void *X, int64_t ld, int es);
 int plan_gemm(int dtype, char ta, char tb, int64_t m, int64_t n, int64_t k, double alpha,
               const void *A, int64_t lda, const void *B, int64_t ldb, double beta, void *C,
               int64_t ldc, int cus, GemmArgs &a, int &trans, bool &vec, int &cfg_id, int &kclass);
-int launch_gemm(const KernelCfg &c, int trans, bool vec, const GemmArgs &a, hipStream_t s);
+// Device workspace handed to a launch: the packed split's operand pieces or
+// split-K's partial tiles live in [ptr, ptr + bytes).
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+int launch_gemm(const KernelCfg &c, int trans, bool vec, const GemmArgs &a, hipStream_t s,
+                Workspace w = Workspace());
+// gemm() with an explicit workspace.  When the planned configuration needs
+// more than w.bytes: reject_short ? GEMM_E_WORKSPACE (nothing launched) : the
+// class's configuration that needs none.  Validation and quick returns as gemm().
+int gemm_ws(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha,
+            const void *A, int64_t lda, const void *B, int64_t ldb, double beta, void *C,
+            int64_t ldc, int dtype, Workspace w, bool reject_short);
+
+// noalloc.hip: the fixed device scratch array of gemm_noalloc (bytes), and
+// the per-device lookup of its address (gemm_init, or the first call).
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+int scratch_device_init(int device);
 
 // grouped.hip
 int grouped_device_init(DevState *d);
@@ -103,6 +121,8 @@ const void *split_pack_entry();
 // stream_workspace returns the stream's reserved buffer when it holds at
 // least `bytes`, else NULL; it never allocates, frees or synchronises.
 void *stream_workspace(DevState *d, hipStream_t s, size_t bytes, int slot = 0);
+// The whole reservation of (s, slot); {NULL, 0} when there is none.
+Workspace stream_reservation(DevState *d, hipStream_t s, int slot = 0);
 // Grows the reservation of (s, slot) to at least `bytes` (allocates; refused
 // during a graph capture).  The replaced buffer is retired, not freed.
 int reserve_workspace(DevState *d, hipStream_t s, size_t bytes, int slot);

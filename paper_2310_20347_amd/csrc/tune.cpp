@@ -154,7 +154,8 @@ extern "C" int gemm_tune_layouts(int dtype, int64_t count, const int64_t *shapes
                     std::vector<float> ms;
                     for (int r = 0; r < reps + 2; ++r) {
                         (void)hipEventRecord(e0, s);
-                        if (launch_gemm(g_cfgs[reg], trans, vec, a, s) != GEMM_OK) break;
+                        if (launch_gemm(g_cfgs[reg], trans, vec, a, s, stream_reservation(d, s)) != GEMM_OK)
+                            break;
                         (void)hipEventRecord(e1, s);
                         if ((e = hipEventSynchronize(e1)) != hipSuccess) return fail(e);
                         float t = 0;
@@ -186,7 +187,9 @@ extern "C" int gemm_tune_layouts(int dtype, int64_t count, const int64_t *shapes
                     const Cand &c = cands[q];
                     for (int r = 0; r < reps; ++r) {
                         (void)hipEventRecord(e0, s);
-                        if (launch_gemm(g_cfgs[c.reg], c.trans, c.vec, c.a, s) != GEMM_OK) break;
+                        if (launch_gemm(g_cfgs[c.reg], c.trans, c.vec, c.a, s, stream_reservation(d, s)) !=
+                            GEMM_OK)
+                            break;
                         (void)hipEventRecord(e1, s);
                         if ((e = hipEventSynchronize(e1)) != hipSuccess) return fail(e);
                         float t = 0;

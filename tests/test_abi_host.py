@@ -130,6 +130,21 @@ def test_panel_occupancy_reproduces_paper_table2():
     assert mg.panel_occupancy(-1, 1, 4, 10) == -1.0
 
 
+def test_noalloc_validates_like_gemm():
+    L = mg.lib()
+
+    def na(ta=b"N", m=4, lda=3, dtype=mg.GEMM_F32, beta=0.0, C=0x3000):
+        return L.gemm_noalloc(ta, b"N", m, 5, 3, 1.0, 0x1000, lda, 0x2000, 5, beta, C, 5, dtype)
+
+    assert na(ta=b"X") == -1
+    assert na(lda=2) == -8
+    assert na(lda=2, dtype=99) == -8
+    assert na(dtype=99) == -14
+    assert na(C=None) == -12
+    assert na(m=0) == 0                              # quick return before any device call
+    assert L.gemm_noalloc_scratch_bytes() == 64 << 20
+
+
 def test_no_device_reports_noinit():
     import torch
     if torch.cuda.is_available():
