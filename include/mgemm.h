@@ -27,11 +27,14 @@
  *   GEMM_F8E4M3:        A, B OCP FP8 E4M3FN bytes;            C float32
  *   GEMM_I8:            A, B int8;                            C int32
  *   GEMM_F64:           A, B float64;                         C float64
+ *   GEMM_I16:           A, B int16;                           C int32
+ *   GEMM_I32:           A, B int32;                           C int32
  *   Accumulation is FP32 for the float types up to FP32, FP64 for GEMM_F64
  *   and INT32 for GEMM_I8.  alpha and beta are passed as double, used as
- *   float32 by the FP32-output paths and as double by GEMM_F64; for GEMM_I8
- *   they must be integers representable in int32 and the epilogue wraps
- *   modulo 2^32 (two's complement).
+ *   float32 by the FP32-output paths and as double by GEMM_F64; for the
+ *   integer types they must be integers representable in int32 and the
+ *   result is the exact integer alpha*op(A)*op(B) + beta*C modulo 2^32
+ *   (two's complement).
  * Pointers: A, B, C are DEVICE pointers owned by the caller, aligned at least
  *   to their element size.  The library never frees or retains them.
  * Semantics (BLAS):
@@ -72,7 +75,12 @@ typedef enum {
                               /* FP64 C; alpha and beta used in full double precision;     */
                               /* gemm() only (the grouped and serving paths return         */
                               /* GEMM_E_UNSUPPORTED / reject it)                           */
-    GEMM_NUM_DTYPES = 9
+    GEMM_I16 = 9,             /* int16 inputs, int32 C: four INT8 MFMA digit products      */
+                              /* and a rank-two correction (or the vector ALUs); exact     */
+                              /* value modulo 2^32; gemm() only                            */
+    GEMM_I32 = 10,            /* int32 inputs and C: ten INT8 MFMA digit products modulo   */
+                              /* 2^32 (or the vector ALUs); gemm() only                    */
+    GEMM_NUM_DTYPES = 11
 } gemm_dtype;
 
 enum {
@@ -287,15 +295,18 @@ int gemm_last_hip_error(void);
  *     whole stages run by separate workgroups, about two per CU, whose
  *     partial tiles go to a per-stream workspace and are then summed in
  *     slice order; deterministic, but float results differ in the last bits
- *     from the unsliced order).
+ *     from the unsliced order), 7 = digit products (GEMM_I16 / GEMM_I32: a
+ *     packing pass writes each operand's int8 digit planes to the workspace,
+ *     then INT8 tiles multiply windows of them, one per weight class).
  *   gemm_config_staging(dtype, id): how the configuration fills its LDS
  *     panels: 0 = global loads through registers (converted, transposed and
  *     stored by the workgroup), 1 = direct global -> LDS loads into a ring of
  *     stages, 2 = packed split (packing pass, then a direct bf16 tile);
  *     packing configurations (paper section 5.3 / 8.6): 3 = A not packed
  *     (its fragments go straight from global memory to registers; B through
- *     LDS), 4 = B not packed, 5 = neither packed (no LDS); negative as
- *     gemm_config_info's errors.
+ *     LDS), 4 = B not packed, 5 = neither packed (no LDS), 6 = digit planes
+ *     (INT16 / INT32: a packing pass writes int8 digit planes, then INT8
+ *     tiles); negative as gemm_config_info's errors.
  *   gemm_config_layouts(dtype, id): bit (2*t + v) is set when the
  *     configuration has a kernel for trans index t = 2*(transA is T) +
  *     (transB is T) with vectorised (v = 1: 16-byte aligned operands and

@@ -17,10 +17,13 @@ GEMM_I8 = 5
 GEMM_F32_BF16X3_ONLY = 6
 GEMM_F32_BF16X6 = 7
 GEMM_F64 = 8
-GEMM_NUM_DTYPES = 9
+GEMM_I16 = 9
+GEMM_I32 = 10
+GEMM_NUM_DTYPES = 11
 DTYPE_NAMES = {GEMM_F32: "f32", GEMM_F32_BF16X3: "bf16x3", GEMM_BF16: "bf16", GEMM_F16: "f16",
                GEMM_F8E4M3: "e4m3", GEMM_I8: "i8", GEMM_F32_BF16X3_ONLY: "bf16x3_only",
-               GEMM_F32_BF16X6: "bf16x6", GEMM_F64: "f64"}
+               GEMM_F32_BF16X6: "bf16x6", GEMM_F64: "f64",
+               GEMM_I16: "i16", GEMM_I32: "i32"}
 
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -328,7 +331,8 @@ def config_info(dtype: int, cfg: int) -> dict:
     keys = ("mc", "nc", "kc", "mr", "nr", "threads", "lds_bytes", "kind")
     info = dict(zip(keys, [int(v) for v in out]))
     st = int(lib().gemm_config_staging(int(dtype), int(cfg)))
-    info["staging"] = (("registers", "direct", "packed", "a_unpacked", "b_unpacked", "unpacked")[st]
+    info["staging"] = (("registers", "direct", "packed", "a_unpacked", "b_unpacked", "unpacked",
+                        "digit_planes")[st]
                        if st >= 0 else None)
     info["layouts"] = int(lib().gemm_config_layouts(int(dtype), int(cfg)))
     return info

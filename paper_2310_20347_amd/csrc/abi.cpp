@@ -52,6 +52,8 @@ int kclass_of(int dtype, int64_t k)
     case GEMM_F8E4M3: return K_F8;
     case GEMM_I8: return K_I8;
     case GEMM_F64: return K_F64;
+    case GEMM_I16: return K_I16;
+    case GEMM_I32: return K_I32;
     default: return -1;
     }
 }
@@ -60,8 +62,9 @@ int elem_bytes(int kclass)
 {
     switch (kclass) {
     case K_F32: case K_SPLIT2: case K_SPLIT3: return 4;
-    case K_BF16: case K_F16: return 2;
+    case K_BF16: case K_F16: case K_I16: return 2;
     case K_F64: return 8;
+    case K_I32: return 4;
     default: return 1;
     }
 }
@@ -99,7 +102,7 @@ int validate(char ta, char tb, int64_t m, int64_t n, int64_t k, double alpha, co
     if (n < 0) return -4;
     if (k < 0) return -5;
     const bool dtype_ok = dtype >= 0 && dtype < GEMM_NUM_DTYPES;
-    const bool is_int = dtype == GEMM_I8;
+    const bool is_int = dtype == GEMM_I8 || dtype == GEMM_I16 || dtype == GEMM_I32;
     if (is_int && !int32_exact(alpha)) return -6;
     const int es = dtype_ok ? elem_bytes(kclass_of(dtype, k)) : 1;
     const bool form = m > 0 && n > 0 && k > 0 && alpha != 0.0;
@@ -185,6 +188,7 @@ void ensure_registered()
     register_direct_byte_late(g_cfgs);
     add_packed(nlate, g_cfgs.size());
     register_f64_late(g_cfgs);
+    register_int_late(g_cfgs);
     for (size_t i = 0; i < g_cfgs.size(); ++i) g_by_class[g_cfgs[i].kclass].push_back((int)i);
     g_registered = true;
 }
@@ -505,6 +509,7 @@ static void packed_sizes(const GemmArgs &a, int64_t &kp, size_t &abytes, size_t 
 
 size_t workspace_need(const KernelCfg &c, const GemmArgs &a, int cus)
 {
+    if (c.kind == 7) return (size_t)digit_layout(c.kclass, a.m, a.n, a.k).total;
     if (c.packed >= 0) {
         int64_t kp;
         size_t ab, bb;
@@ -522,6 +527,7 @@ size_t workspace_need(const KernelCfg &c, const GemmArgs &a, int cus)
 int no_workspace_id(int kclass, int reg, bool vec)
 {
     const KernelCfg &c = g_cfgs[reg];
+    if (c.kind == 7) return 0;               // the vector-ALU tile
     if (c.packed >= 0) return vec ? 1 : 0;   // the fused split tile
     if (c.base >= 0) {
         const std::vector<int> &ids = g_by_class[kclass];
@@ -597,6 +603,7 @@ int launch_gemm(const KernelCfg &c, int trans, bool vec, const GemmArgs &a, hipS
 {
     if (c.packed >= 0) return launch_packed(c, trans, a, s, w);
     if (c.base >= 0) return launch_splitk(c, trans, vec, a, s, w);
+    if (c.kind == 7) return launch_digits(c, a, trans, s, w);
     const void *f = c.func[trans][vec ? 1 : 0];
     if (!f) return GEMM_E_UNSUPPORTED;
     const int64_t blocks = int64_t(a.tiles_m) * a.tiles_n;
@@ -655,8 +662,9 @@ int plan_gemm(int dtype, char ta, char tb, int64_t m, int64_t n, int64_t k, doub
     a.k = (int)k;
     a.alpha = (float)alpha;
     a.beta = (float)beta;
-    a.ialpha = dtype == GEMM_I8 ? (int)alpha : 0;
-    a.ibeta = dtype == GEMM_I8 ? (int)beta : 0;
+    const bool int_out = dtype == GEMM_I8 || dtype == GEMM_I16 || dtype == GEMM_I32;
+    a.ialpha = int_out ? (int)alpha : 0;
+    a.ibeta = int_out ? (int)beta : 0;
     a.tiles_m = (int)((m + c.mc - 1) / c.mc);
     a.tiles_n = (int)((n + c.nc - 1) / c.nc);
     a.order = order;
@@ -682,7 +690,9 @@ int gemm_ws(char transA, char transB, int64_t m, int64_t n, int64_t k, double al
     if (rc != GEMM_OK) return rc;
     hipStream_t s = t_tls.stream;
     if (alpha == 0.0 || k == 0) {
-        launch_scale(C, ldc, (int)m, (int)n, beta, dtype == GEMM_I8 ? 1 : (dtype == GEMM_F64 ? 2 : 0), s);
+        const int elem = (dtype == GEMM_I8 || dtype == GEMM_I16 || dtype == GEMM_I32) ? 1
+                         : (dtype == GEMM_F64 ? 2 : 0);
+        launch_scale(C, ldc, (int)m, (int)n, beta, elem, s);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) {
             t_tls.hip_err = (int)e;
@@ -904,6 +914,7 @@ int gemm_config_staging(int dtype, int id)
     const std::vector<int> &ids = g_by_class[class_for_query(dtype)];
     if (id < 0 || id >= (int)ids.size()) return -2;
     const KernelCfg &c = g_cfgs[ids[id]];
+    if (c.kind == 7) return 6;
     if (c.unpacked) return 2 + c.unpacked;
     return c.packed >= 0 ? 2 : (c.direct ? 1 : 0);
 }

@@ -102,6 +102,17 @@ int gemm_ws(char transA, char transB, int64_t m, int64_t n, int64_t k, double al
             const void *A, int64_t lda, const void *B, int64_t ldb, double beta, void *C,
             int64_t ldc, int dtype, Workspace w, bool reject_short);
 
+// kernels_int.hip: INT16 / INT32 digit products.  Workspace layout of one
+// call: A's planes (m rows of P*kp int8), B's (n rows), then (INT16) the
+// row sums of op(A) and column sums of op(B) (int32).
+struct DigitLayout {
+    int P = 0;           // digit planes per operand (2 or 4)
+    int64_t kp = 0;      // k rounded up to 64
+    int64_t a_off = 0, b_off = 0, sums_off = 0, total = 0;   // bytes
+};
+DigitLayout digit_layout(int kclass, int64_t m, int64_t n, int64_t k);
+int launch_digits(const KernelCfg &c, const GemmArgs &a, int trans, hipStream_t s, Workspace w);
+
 // noalloc.hip: the fixed device scratch array of gemm_noalloc (bytes), and
 // the per-device lookup of its address (gemm_init, or the first call).
 constexpr size_t kNoallocScratchBytes = size_t(64) << 20;

@@ -138,8 +138,8 @@ __device__ __forceinline__ uint8_t e4m3_trunc(float v)
 // values (the sum of four uniforms, scaled to unit variance) in the float
 // formats, as the benchmark's precision workload draws them (the
 // power-limited low-precision kernels run at a clock that depends on the
-// data), and arbitrary bytes for int8.  kind: 0 f32, 1 bf16, 2 f16, 3 e4m3,
-// 4 int8, 5 f64.
+// data), and arbitrary bytes for int8, int16 and int32.  kind: 0 f32,
+// 1 bf16, 2 f16, 3 e4m3, 4 int8, 5 f64, 6 int16, 7 int32.
 __global__ void fill_kernel(void *p, int64_t count, int kind, uint32_t seed)
 {
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count;
@@ -154,6 +154,8 @@ __global__ void fill_kernel(void *p, int64_t count, int kind, uint32_t seed)
         case 2: ((_Float16 *)p)[t] = (_Float16)v; break;
         case 3: ((uint8_t *)p)[t] = e4m3_trunc(v); break;
         case 5: ((double *)p)[t] = (double)v; break;
+        case 6: ((int16_t *)p)[t] = (int16_t)(h & 0xFFFFu); break;
+        case 7: ((int32_t *)p)[t] = (int32_t)(h ^ (g << 16)); break;
         default: ((int8_t *)p)[t] = (int8_t)(h & 0xFFu); break;
         }
     }

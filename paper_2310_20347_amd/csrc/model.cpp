@@ -41,6 +41,11 @@ double rate_per_cu(int kclass)
     case K_BF16: case K_F16: return 4096;
     case K_F8: case K_I8: return 8192;
     case K_F64: return 128;
+    // INT16 / INT32 on the vector ALUs (configuration 0): a 24-bit
+    // multiply-add per int16 product, a quarter-rate 32-bit multiply and an
+    // add per int32 product, each value read from LDS
+    case K_I16: return 64;
+    case K_I32: return 24;
     default: return 256;
     }
 }
@@ -75,6 +80,16 @@ int vgprs_of(const KernelCfg &c, int kclass)
 double model_cycles(const KernelCfg &c, int kclass, int64_t m, int64_t n, int64_t k, int cus)
 {
     if (m <= 0 || n <= 0 || k <= 0 || c.mc <= 0 || c.nc <= 0 || c.kc <= 0 || cus <= 0) return 0;
+    if (c.kind == 7) {
+        // digit products: INT8 GEMMs over products x k (at about half the
+        // INT8 MFMA rate), the packing pass (operands read, digit planes
+        // written) and one pass over C per weight class
+        const double products = kclass == K_I16 ? 4 : 10, classes = kclass == K_I16 ? 4 : 4;
+        const double P = kclass == K_I16 ? 2 : 4;
+        const double t_mma = 2.0 * m * n * k * products / (rate_per_cu(K_I8) * 0.5 * cus);
+        const double bytes = double(m + n) * k * (elem_bytes(kclass) + P) + classes * 8.0 * m * n;
+        return t_mma + bytes / kHbmBytesPerClk + classes * kLoadLatency * 2;
+    }
     const int waves = std::max(1, c.threads / 64);
     // workgroups per compute unit
     const int occ_lds = c.lds > 0 ? kLdsBytes / c.lds : 8;

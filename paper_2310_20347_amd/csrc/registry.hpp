@@ -18,7 +18,7 @@
 namespace mg {
 
 // Kernel dtype classes (the ABI's split dtype maps to SPLIT2 or SPLIT3).
-enum KClass { K_F32 = 0, K_SPLIT2, K_SPLIT3, K_BF16, K_F16, K_F8, K_I8, K_F64, K_NUM };
+enum KClass { K_F32 = 0, K_SPLIT2, K_SPLIT3, K_BF16, K_F16, K_F8, K_I8, K_F64, K_I16, K_I32, K_NUM };
 
 struct KernelCfg {
     int kclass = 0;
@@ -27,7 +27,8 @@ struct KernelCfg {
     int threads = 0;
     int lds = 0;            // bytes of LDS per workgroup
     int stages = 0;
-    int kind = 0;           // 0: C resident; 1..4: operand resident; 5: packed split; 6: split-K
+    int kind = 0;           // 0: C resident; 1..4: operand resident; 5: packed split; 6: split-K;
+                            // 7: digit products (INT16 / INT32 on the INT8 tiles)
     bool direct = false;    // stages fed by direct global -> LDS loads
     int packed = -1;        // packed split: registry index of the bf16 tile run on the packed operands
     int base = -1;          // split-K: registry index of the tile it slices
@@ -56,6 +57,7 @@ void register_direct_f32_late(std::vector<KernelCfg> &out);
 void register_direct_half_late(std::vector<KernelCfg> &out);
 void register_direct_byte_late(std::vector<KernelCfg> &out);
 void register_f64_late(std::vector<KernelCfg> &out);
+void register_int_late(std::vector<KernelCfg> &out);
 void register_direct_half(std::vector<KernelCfg> &out);
 void register_direct_byte(std::vector<KernelCfg> &out);
 void register_nopack(std::vector<KernelCfg> &out);

@@ -33,6 +33,8 @@ static int fill_kind(int kclass)
     case K_F16: return 2;
     case K_F8: return 3;
     case K_F64: return 5;
+    case K_I16: return 6;
+    case K_I32: return 7;
     default: return 4;
     }
 }

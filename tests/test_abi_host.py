@@ -113,6 +113,8 @@ def test_strerror_and_config_introspection():
             info = mg.config_info(dt, c)
             assert info["mc"] % info["mr"] == 0 and info["nc"] % info["nr"] == 0
             assert info["lds_bytes"] <= 160 * 1024
+            if dt in (mg.GEMM_I16, mg.GEMM_I32):
+                continue   # vector-ALU tile (16 values of k per stage) and digit products
             # a stage holds 128 bytes of k per panel row (64 for the deep-ring
             # direct configurations)
             kb = info["kc"] * {0: 4, 1: 2, 2: 2, 3: 2, 4: 1, 5: 1, 6: 2, 7: 2, 8: 8}[dt]
@@ -128,6 +130,29 @@ def test_panel_occupancy_reproduces_paper_table2():
         # the table prints 3 significant figures (e.g. 18.75 -> 18.80)
         assert float(f"{got:.3g}") == pct, (layer, kc, nr, got, pct)
     assert mg.panel_occupancy(-1, 1, 4, 10) == -1.0
+
+
+def test_integer_dtypes_validate_on_the_host():
+    # INT16 / INT32: integer alpha and beta (-6, -11), element alignment of A (-7)
+    assert call(dtype=mg.GEMM_I16, alpha=0.5) == -6
+    assert call(dtype=mg.GEMM_I32, beta=1.5) == -11
+    assert call(dtype=mg.GEMM_I32, alpha=2.0 ** 31) == -6
+    assert call(dtype=mg.GEMM_I16, A=0x1001) == -7
+    assert call(dtype=mg.GEMM_I32, A=0x1002) == -7
+    assert call(dtype=mg.GEMM_I16, m=0) == 0
+    # two configurations each: the vector-ALU tile (every layout, any
+    # alignment) and the digit products (kind 7)
+    for dt in (mg.GEMM_I16, mg.GEMM_I32):
+        assert mg.num_configs(dt) == 2
+        assert mg.config_info(dt, 0)["kind"] == 0
+        assert mg.config_info(dt, 1)["kind"] == 7
+        assert mg.lib().gemm_config_layouts(dt, 0) == 255
+        assert mg.lib().gemm_config_layouts(dt, 1) == 255
+    # the grouped launch does not take them
+    P = mg._binding._Problem
+    arr = (P * 1)()
+    arr[0] = P(b"N", b"N", 4, 5, 3, 1.0, 0x1000, 3, 0x2000, 5, 0.0, 0x3000, 5)
+    assert mg.lib().gemm_grouped(1, arr, mg.GEMM_I16) == 2   # GEMM_E_UNSUPPORTED
 
 
 def test_noalloc_validates_like_gemm():
