@@ -226,6 +226,42 @@ int64_t gemm_grouped_capacity(void);
  *     a slot only while no launch or replay that uses it is in flight.
  *   gemm_grouped_slot_destroy(slot): synchronises the slot's device and frees it.
  */
+/*
+ * Tile bodies of the grouped kernel for batches of 'N','N' problems with
+ * 16-byte aligned operands and leading dimensions (the compact kernel).
+ * The paper's finding that the best micro-kernel depends on the operand
+ * shape (section 8.4, "In search of the best micro-kernel") applies per
+ * problem: each problem of such a batch runs the body chosen for its size
+ * bucket by gemm_tune_grouped (tuning-table entries with "trans": 4), or,
+ * without an entry near the bucket, the body whose tile fits m and n best
+ * (32 or 64 rows / columns up to that size, then 128, then 256).  The
+ * split dtype uses three-term bodies for k >= 64 and six-term ones below.
+ *   gemm_grouped_num_bodies(dtype): number of bodies of the dtype's family
+ *     (-1 for a dtype the grouped kernel does not take).
+ *   gemm_grouped_body_info(dtype, body, out[3]): {mc, nc, split pieces
+ *     (2: three terms, 3: six terms, 0: not a split dtype)}.
+ *   gemm_grouped_force_body(body): this thread's later grouped tables use
+ *     `body` for every problem it qualifies for (-1 clears; other values
+ *     below -1 or from 8 on return -1).
+ *   gemm_grouped_bodies(count, problems, dtype, bodies): validates like
+ *     gemm_grouped and writes the body each problem would run (-1: skipped
+ *     as a quick return, or the batch takes the general kernel); launches
+ *     nothing.
+ *   gemm_tune_grouped(dtype, count, shapes, reps, out_path): for every
+ *     (m, n, k) of `shapes` (3*count values, each 1..65536) times a batch of
+ *     identical problems of that size in one launch with each qualifying
+ *     body (median of `reps` launches), stores the fastest per size bucket
+ *     and writes the table to `out_path` (NULL: memory only).  Synchronous;
+ *     allocates its operands, a 1 GiB output region and a private stream,
+ *     all freed before it returns.
+ */
+int gemm_grouped_num_bodies(int dtype);
+int gemm_grouped_body_info(int dtype, int body, int64_t out[3]);
+int gemm_grouped_force_body(int body);
+int gemm_grouped_bodies(int64_t count, const gemm_problem *problems, int dtype, int *bodies);
+int gemm_tune_grouped(int dtype, int64_t count, const int64_t *shapes, int reps,
+                      const char *out_path);
+
 int gemm_grouped_slot_create(void **slot, int64_t capacity);
 int gemm_grouped_slot_write(void *slot, int64_t count, const gemm_problem *problems,
                             int dtype);

@@ -81,6 +81,16 @@ def lib():
     L.gemm_noalloc_scratch_bytes.restype = _I64
     L.gemm_grouped.argtypes = [_I64, ctypes.POINTER(_Problem), _INT]
     L.gemm_grouped.restype = _INT
+    L.gemm_grouped_num_bodies.argtypes = [_INT]
+    L.gemm_grouped_num_bodies.restype = _INT
+    L.gemm_grouped_body_info.argtypes = [_INT, _INT, ctypes.POINTER(_I64)]
+    L.gemm_grouped_body_info.restype = _INT
+    L.gemm_grouped_force_body.argtypes = [_INT]
+    L.gemm_grouped_force_body.restype = _INT
+    L.gemm_grouped_bodies.argtypes = [_I64, ctypes.POINTER(_Problem), _INT, ctypes.POINTER(_INT)]
+    L.gemm_grouped_bodies.restype = _INT
+    L.gemm_tune_grouped.argtypes = [_INT, _I64, ctypes.POINTER(_I64), _INT, ctypes.c_char_p]
+    L.gemm_tune_grouped.restype = _INT
     L.gemm_grouped_capacity.argtypes = []
     L.gemm_grouped_capacity.restype = _I64
     L.gemm_grouped_slot_create.argtypes = [ctypes.POINTER(_P), _I64]
@@ -257,6 +267,43 @@ def gemm_grouped(problems, dtype: int, stream: Any = None, check: bool = True) -
         problems = PackedProblems(problems)
     rc = lib().gemm_grouped(problems.count, problems.array, int(dtype))
     return _check(rc, "gemm_grouped") if check else rc
+
+
+def grouped_bodies_info(dtype: int) -> list:
+    """The grouped compact kernel's tile bodies of the dtype's family:
+    [{"mc", "nc", "pieces"}, ...]."""
+    n = int(lib().gemm_grouped_num_bodies(int(dtype)))
+    if n < 0:
+        raise MGemmError(-1, "gemm_grouped_num_bodies")
+    out = []
+    for b in range(n):
+        v = (_I64 * 3)()
+        _check(lib().gemm_grouped_body_info(int(dtype), b, v), "gemm_grouped_body_info")
+        out.append({"mc": int(v[0]), "nc": int(v[1]), "pieces": int(v[2])})
+    return out
+
+
+def grouped_force_body(body: int) -> None:
+    """Pin this thread's grouped tables to one body (-1 clears)."""
+    _check(lib().gemm_grouped_force_body(int(body)), "gemm_grouped_force_body")
+
+
+def grouped_bodies(problems, dtype: int) -> list:
+    """The body each problem would run (-1: none), without launching."""
+    if not isinstance(problems, PackedProblems):
+        problems = PackedProblems(problems)
+    out = (_INT * max(1, problems.count))()
+    _check(lib().gemm_grouped_bodies(problems.count, problems.array, int(dtype), out),
+           "gemm_grouped_bodies")
+    return [int(out[i]) for i in range(problems.count)]
+
+
+def gemm_tune_grouped(dtype: int, shapes, reps: int = 5, out_path: Optional[str] = None) -> None:
+    """Times every body on a batch of each shape; stores the fastest per bucket."""
+    flat = (_I64 * max(1, 3 * len(shapes)))(*[int(v) for s in shapes for v in s])
+    p = out_path.encode() if out_path else None
+    _check(lib().gemm_tune_grouped(int(dtype), len(shapes), flat, int(reps), p),
+           "gemm_tune_grouped")
 
 
 def gemm_grouped_capacity() -> int:

@@ -253,10 +253,11 @@ static bool parse_entry(const std::string &obj, TuneKey &key, TuneVal &val)
     num("us", us);
     key = TuneKey{(int)kc, (int)tr, (int)bm, (int)bn, (int)bk};
     val = TuneVal{(int)cfg, (int)order, (int)group, us};
-    return key.kclass >= 0 && key.kclass < K_NUM && key.trans >= 0 && key.trans < 4;
+    return key.kclass >= 0 && key.kclass < K_NUM && key.trans >= 0 && key.trans <= kGroupedTrans;
 }
 
 static void rebuild_lut_locked();
+static void ensure_table();
 
 int load_table(const char *path)
 {
@@ -276,8 +277,10 @@ int load_table(const char *path)
         TuneKey key;
         TuneVal val;
         if (!parse_entry(s.substr(a, b - a + 1), key, val)) return GEMM_E_TUNE_TABLE;
-        if (val.cfg < 0 || val.cfg >= (int)g_by_class[key.kclass].size() || val.group < 1 ||
-            val.order < 0 || val.order > 1)
+        // a grouped entry names a body of the class's grouped kernel
+        const int ncfg = key.trans == kGroupedTrans ? kMaxGroupedBodies
+                                                    : (int)g_by_class[key.kclass].size();
+        if (val.cfg < 0 || val.cfg >= ncfg || val.group < 1 || val.order < 0 || val.order > 1)
             return GEMM_E_TUNE_TABLE;
         table[key] = val;
         p = b + 1;
@@ -315,6 +318,7 @@ int save_table(const char *path)
 // an entry of another transposition counting half a step more), or cfg -1
 // when none is near (the heuristic decides).
 static std::vector<TuneVal> g_lut;
+static std::vector<int> g_glut;   // grouped bodies: [class][bm][bn][bk], -1 = none near
 constexpr int kNB = 9;   // buckets 4..12
 static size_t lut_index(int kclass, int trans, int bm, int bn, int bk)
 {
@@ -333,7 +337,7 @@ static void rebuild_lut_locked()
                         TuneVal v{-1, 0, 8, 0.0};
                         for (auto &kv : g_table) {
                             const TuneKey &t = kv.first;
-                            if (t.kclass != kc) continue;
+                            if (t.kclass != kc || t.trans == kGroupedTrans) continue;
                             // an entry tuned for another layout only counts
                             // when its configuration has a kernel for this one
                             if (t.trans != tr && kv.second.cfg >= 0 &&
@@ -349,6 +353,41 @@ static void rebuild_lut_locked()
                         }
                         if (best <= 3.5) g_lut[lut_index(kc, tr, bm, bn, bk)] = v;
                     }
+    // grouped bodies: the nearest grouped entry of the class
+    g_glut.assign((size_t)K_NUM * kNB * kNB * kNB, -1);
+    for (int kc = 0; kc < K_NUM; ++kc)
+        for (int bm = 4; bm <= 12; ++bm)
+            for (int bn = 4; bn <= 12; ++bn)
+                for (int bk = 4; bk <= 12; ++bk) {
+                    double best = 1e9;
+                    int body = -1;
+                    for (auto &kv : g_table) {
+                        const TuneKey &t = kv.first;
+                        if (t.kclass != kc || t.trans != kGroupedTrans) continue;
+                        const double d = std::abs(t.bm - bm) + std::abs(t.bn - bn) + std::abs(t.bk - bk);
+                        if (d < best) {
+                            best = d;
+                            body = kv.second.cfg;
+                        }
+                    }
+                    if (best <= 3.5)
+                        g_glut[(((size_t)kc * kNB + (bm - 4)) * kNB + (bn - 4)) * kNB + (bk - 4)] = body;
+                }
+}
+
+int grouped_body_lookup(int kclass, int64_t m, int64_t n, int64_t k)
+{
+    ensure_table();
+    std::lock_guard<std::mutex> g(g_mu);
+    if (g_glut.empty() || kclass < 0 || kclass >= K_NUM) return -1;
+    return g_glut[(((size_t)kclass * kNB + (bucket(m) - 4)) * kNB + (bucket(n) - 4)) * kNB +
+                  (bucket(k) - 4)];
+}
+
+void set_table_entry(const TuneKey &key, const TuneVal &val)
+{
+    std::lock_guard<std::mutex> g(g_mu);
+    g_table[key] = val;
 }
 
 void rebuild_lut()

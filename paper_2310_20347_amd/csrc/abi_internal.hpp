@@ -39,6 +39,10 @@ struct DevState {
 constexpr int kPackUnavailable = 100;
 
 // Tuning table key: kernel class, trans index (2*tA + tB), log2 size buckets.
+// Entries with trans == kGroupedTrans choose the grouped kernel's tile body
+// for the bucket (cfg = body index, below kMaxGroupedBodies).
+constexpr int kGroupedTrans = 4;
+constexpr int kMaxGroupedBodies = 8;
 struct TuneKey {
     int kclass, trans, bm, bn, bk;
     bool operator<(const TuneKey &o) const
@@ -57,6 +61,7 @@ struct Tls {
     int force_id[K_NUM];
     int force_order[K_NUM];
     int force_group = 0;
+    int force_body = -1;      // grouped kernel: body for every problem (-1: per bucket)
     int64_t last[4];
     int hip_err = 0;
     Tls();
@@ -79,6 +84,10 @@ int validate(char ta, char tb, int64_t m, int64_t n, int64_t k, double alpha, co
 void ensure_registered();
 int device_state(DevState **out);
 int load_table(const char *path);
+// Tuned grouped body of (class, size bucket), or -1 when no entry is near.
+int grouped_body_lookup(int kclass, int64_t m, int64_t n, int64_t k);
+// Adds or replaces one tuning-table entry (call rebuild_lut afterwards).
+void set_table_entry(const TuneKey &key, const TuneVal &val);
 int save_table(const char *path);
 void rebuild_lut();
 void select_config(int kclass, int trans, int64_t m, int64_t n, int64_t k, int cus, int &id,
@@ -117,6 +126,10 @@ int launch_digits(const KernelCfg &c, const GemmArgs &a, int trans, hipStream_t 
 // the per-device lookup of its address (gemm_init, or the first call).
 constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
 int scratch_device_init(int device);
+
+// misc.hip: fills `count` elements of the tuner's operands (kind: 0 f32,
+// 1 bf16, 2 f16, 3 e4m3, 4 int8, 5 f64, 6 int16, 7 int32).
+void launch_fill(void *p, int64_t count, int kind, uint32_t seed, hipStream_t s);
 
 // grouped.hip
 int grouped_device_init(DevState *d);

@@ -145,4 +145,27 @@ __device__ __forceinline__ float bf16_val(u32 b)
     return __builtin_bit_cast(float, b << 16);
 }
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// The P bf16 pieces of the pair (x0, x1), round-to-nearest-even at each step
+// (the same values as bf16_bits / bf16_val one at a time): piece p of x0 in
+// the low half of out[p], of x1 in the high half.  Both values convert in
+// one instruction (v_cvt_pk_bf16_f32), and the pieces come back to FP32 as
+// a shift and a mask of the packed word.
+template <int P>
+__device__ __forceinline__ void split_pair(float x0, float x1, u32 (&out)[P])
+{
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const f32x2_t v = {x0, x1};
+        const u32 h = __builtin_bit_cast(u32, __builtin_convertvector(v, bf16x2_t));
+        out[p] = h;
+        if (p + 1 < P) {
+            x0 -= __builtin_bit_cast(float, h << 16);
+            x1 -= __builtin_bit_cast(float, h & 0xFFFF0000u);
+        }
+    }
+}
+
 } // namespace mg

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -157,13 +158,42 @@ static int ensure_grouped(DevState **out)
     return GEMM_OK;
 }
 
+// Lean body of one problem: the body pinned on this thread
+// (gemm_grouped_force_body), else the tuning table's grouped entry for the
+// size bucket (gemm_tune_grouped), else the body whose tile fits the problem
+// best: 32 or 64 rows (columns) for m (n) up to that, 128, and 256 from 1024
+// on where such a body exists.  Split family: only bodies of the problem's
+// term count (three terms for k >= 64, six below) qualify.
+static int lean_body(const GroupedFamily &F, int kclass, int64_t m, int64_t n, int64_t k)
+{
+    const int want_pieces = kclass == K_SPLIT2 ? 2 : kclass == K_SPLIT3 ? 3 : 0;
+    auto ok = [&](int b) { return b >= 0 && b < F.lean_n && F.lean_pieces[b] == want_pieces; };
+    if (ok(t_tls.force_body)) return t_tls.force_body;
+    const int tuned = grouped_body_lookup(kclass, m, n, k);
+    if (ok(tuned)) return tuned;
+    auto want = [](int64_t x) { return x <= 32 ? 32.0 : x <= 64 ? 64.0 : x < 1024 ? 128.0 : 256.0; };
+    const double wm = want(m), wn = want(n);
+    int best = -1;
+    double bd = 1e300;
+    for (int b = 0; b < F.lean_n; ++b) {
+        if (!ok(b)) continue;
+        const double d = std::fabs(std::log2(F.lean_mc[b] / wm)) + std::fabs(std::log2(F.lean_nc[b] / wn));
+        if (d < bd - 1e-9) {
+            bd = d;
+            best = b;
+        }
+    }
+    return best;
+}
+
 // Builds the descriptor table of `count` problems into `table` (host memory).
 // `want`: -1 choose, 0 full kernel, 1 lean kernel.  The lean kernel serves
 // batches whose problems are all 'N','N' with vectorisable operands; *variant
 // receives the kernel the table was built for.  Returns 0 / -(1000*p + i) /
 // GEMM_E_*; sets total tiles in the header.
-static int build_table(const GroupedDev *gd, int cus, int64_t count, const gemm_problem *pr,
-                       int dtype, char *table, int want, int *variant, int64_t cap)
+static int build_table(const GroupedFamily *fams, int cus, int64_t count, const gemm_problem *pr,
+                       int dtype, char *table, int want, int *variant, int64_t cap,
+                       int *bodies = nullptr)
 {
     if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -3;
     if (count < 0) return -1;
@@ -171,7 +201,7 @@ static int build_table(const GroupedDev *gd, int cus, int64_t count, const gemm_
     if (count > kCapacity) return GEMM_E_WORKSPACE;
     const int fam = family_of(dtype);
     if (fam < 0) return GEMM_E_UNSUPPORTED;
-    const GroupedFamily &F = gd->fam[fam];
+    const GroupedFamily &F = fams[fam];
     for (int64_t p = 0; p < count; ++p) {
         const gemm_problem &q = pr[p];
         const int v = validate(q.transA, q.transB, q.m, q.n, q.k, q.alpha, q.A, q.lda, q.B, q.ldb,
@@ -195,6 +225,7 @@ static int build_table(const GroupedDev *gd, int cus, int64_t count, const gemm_
     tmp.reserve((size_t)count);
     for (int64_t p = 0; p < count; ++p) {
         const gemm_problem &q = pr[p];
+        if (bodies) bodies[p] = -1;
         if (q.m == 0 || q.n == 0) continue;
         if ((q.alpha == 0.0 || q.k == 0) && q.beta == 1.0) continue;
         const bool ta = q.transA == 'T' || q.transA == 't' || q.transA == 'C' || q.transA == 'c';
@@ -207,9 +238,11 @@ static int build_table(const GroupedDev *gd, int cus, int64_t count, const gemm_
         const int es = elem_bytes(kclass);
         const bool vec = vec_ok(q.A, q.lda, es) && vec_ok(q.B, q.ldb, es);
         if (lean) {
-            shape = kclass == K_SPLIT3 ? 1 : 0;
+            shape = lean_body(F, kclass, q.m, q.n, q.k);
+            if (shape < 0) return GEMM_E_UNSUPPORTED;
             mc = F.lean_mc[shape];
             nc = F.lean_nc[shape];
+            if (bodies) bodies[p] = shape;
         } else {
             if (kclass == K_SPLIT3)
                 shape = 2;
@@ -324,7 +357,7 @@ int gemm_grouped(int64_t count, const gemm_problem *problems, int dtype)
         }
     }
     int variant = 0;
-    rc = build_table(gd, d->cus, count, problems, dtype, s.host, -1, &variant, 0);
+    rc = build_table(gd->fam, d->cus, count, problems, dtype, s.host, -1, &variant, 0);
     if (rc != GEMM_OK) return rc;
     const GHeader *h = (const GHeader *)s.host;
     if (h->total_tiles == 0) {
@@ -385,7 +418,7 @@ int gemm_grouped_slot_write(void *slot, int64_t count, const gemm_problem *probl
     // build into a private buffer first so a failed validation leaves the slot intact
     std::vector<char> buf(table_bytes(s->capacity));
     int variant = 0;
-    rc = build_table((GroupedDev *)d->grouped, d->cus, count, problems, dtype, buf.data(),
+    rc = build_table(((GroupedDev *)d->grouped)->fam, d->cus, count, problems, dtype, buf.data(),
                      s->variant, &variant, s->capacity);
     if (rc != GEMM_OK) {
         // a problem error is reported as in gemm_grouped: -(1000*p + i)
@@ -411,6 +444,190 @@ int gemm_grouped_slot_launch(void *slot)
     const size_t bytes = table_bytes(s->capacity);
     return launch_table(gd, *s, s->family, s->variant, gd->grid[s->family][s->variant], bytes,
                         t_tls.stream);
+}
+
+int gemm_grouped_num_bodies(int dtype)
+{
+    if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -1;
+    const int fam = family_of(dtype);
+    if (fam < 0) return -1;
+    return grouped_family(fam).lean_n;
+}
+
+int gemm_grouped_body_info(int dtype, int body, int64_t out[3])
+{
+    if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -1;
+    const int fam = family_of(dtype);
+    if (fam < 0) return GEMM_E_UNSUPPORTED;
+    const GroupedFamily F = grouped_family(fam);
+    if (body < 0 || body >= F.lean_n) return -2;
+    if (!out) return -3;
+    out[0] = F.lean_mc[body];
+    out[1] = F.lean_nc[body];
+    out[2] = F.lean_pieces[body];
+    return GEMM_OK;
+}
+
+int gemm_grouped_force_body(int body)
+{
+    if (body < -1 || body >= kMaxGroupedBodies) return -1;
+    t_tls.force_body = body;
+    return GEMM_OK;
+}
+
+int gemm_grouped_bodies(int64_t count, const gemm_problem *problems, int dtype, int *bodies)
+{
+    if (count < 0) return -1;
+    if (count > 0 && !problems) return -2;
+    if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -3;
+    if (count > 0 && !bodies) return -4;
+    const int fam = family_of(dtype);
+    if (fam < 0) return GEMM_E_UNSUPPORTED;
+    if (count > kCapacity) return GEMM_E_WORKSPACE;
+    ensure_registered();
+    GroupedFamily fams[G_NUM];
+    for (int f = 0; f < G_NUM; ++f) fams[f] = grouped_family(f);
+    int cus = 256;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices && g_dev[dev].init)
+        cus = g_dev[dev].cus;
+    std::vector<char> buf(table_bytes(std::max<int64_t>(count, 1)));
+    int variant = 0;
+    return build_table(fams, cus, count, problems, dtype, buf.data(), -1, &variant, 0, bodies);
+}
+
+int gemm_tune_grouped(int dtype, int64_t count, const int64_t *shapes, int reps,
+                      const char *out_path)
+{
+    if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -1;
+    if (count < 1) return -2;
+    if (!shapes) return -3;
+    if (reps < 1) return -4;
+    const int fam = family_of(dtype);
+    if (fam < 0) return GEMM_E_UNSUPPORTED;
+    for (int64_t i = 0; i < 3 * count; ++i)
+        if (shapes[i] < 1 || shapes[i] > 65536) return -3;
+    DevState *d = nullptr;
+    int rc = ensure_grouped(&d);
+    if (rc != GEMM_OK) return rc;
+    GroupedDev *gd = (GroupedDev *)d->grouped;
+    const GroupedFamily &F = gd->fam[fam];
+    // one private slot, operands shared by every problem of a batch, and a C
+    // region per problem
+    constexpr size_t kCBytes = size_t(1) << 30;
+    size_t maxA = 16, maxB = 16;
+    for (int64_t i = 0; i < count; ++i) {
+        const int64_t m = shapes[3 * i], n = shapes[3 * i + 1], k = shapes[3 * i + 2];
+        const int es = elem_bytes(kclass_of(dtype, k));
+        const int64_t al = 16 / es;
+        maxA = std::max(maxA, size_t(m * ((k + al - 1) / al * al) * es));
+        maxB = std::max(maxB, size_t(k * ((n + al - 1) / al * al) * es));
+    }
+    Slot s;
+    void *A = nullptr, *B = nullptr, *C = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const int saved_body = t_tls.force_body;
+    auto cleanup = [&]() {
+        if (st) (void)hipStreamSynchronize(st);
+        slot_free(s);
+        if (A) (void)hipFree(A);
+        if (B) (void)hipFree(B);
+        if (C) (void)hipFree(C);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (st) (void)hipStreamDestroy(st);
+        t_tls.force_body = saved_body;
+    };
+    hipError_t e = hipSuccess;
+    if ((rc = slot_alloc(s, d->device)) != GEMM_OK) {
+        cleanup();
+        return rc;
+    }
+    if ((e = hipMalloc(&A, maxA)) != hipSuccess || (e = hipMalloc(&B, maxB)) != hipSuccess ||
+        (e = hipMalloc(&C, kCBytes)) != hipSuccess || (e = hipStreamCreate(&st)) != hipSuccess ||
+        (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        t_tls.hip_err = (int)e;
+        cleanup();
+        return GEMM_E_HIP;
+    }
+    const int ckind = fam == G_I8 ? 4 : fam == G_BF16 ? 1 : fam == G_F16 ? 2 : fam == G_F8 ? 3 : 0;
+    launch_fill(A, (int64_t)(maxA / (ckind == 0 ? 4 : ckind <= 2 ? 2 : 1)), ckind, 5u, st);
+    launch_fill(B, (int64_t)(maxB / (ckind == 0 ? 4 : ckind <= 2 ? 2 : 1)), ckind, 6u, st);
+    std::vector<gemm_problem> probs;
+    for (int64_t i = 0; i < count; ++i) {
+        const int64_t m = shapes[3 * i], n = shapes[3 * i + 1], k = shapes[3 * i + 2];
+        const int kclass = kclass_of(dtype, k);
+        const int es = elem_bytes(kclass);
+        const int64_t al = 16 / es;
+        const int64_t lda = (k + al - 1) / al * al, ldb = (n + al - 1) / al * al;
+        // enough problems for about four tiles per workgroup slot of the
+        // 128x128 body, within the C region and the table
+        const int64_t tiles128 = ((m + 127) / 128) * ((n + 127) / 128);
+        int64_t N = std::max<int64_t>(1, (4 * int64_t(gd->grid[fam][1]) + tiles128 - 1) / tiles128);
+        N = std::min<int64_t>({N, 512, std::max<int64_t>(1, int64_t(kCBytes / (size_t(m) * n * 4)))});
+        probs.assign((size_t)N, gemm_problem());
+        for (int64_t p = 0; p < N; ++p) {
+            gemm_problem &q = probs[(size_t)p];
+            q.transA = 'N';
+            q.transB = 'N';
+            q.m = m;
+            q.n = n;
+            q.k = k;
+            q.alpha = 1.0;
+            q.A = A;
+            q.lda = lda;
+            q.B = B;
+            q.ldb = ldb;
+            q.beta = 0.0;
+            q.C = (char *)C + size_t(p) * m * n * 4;
+            q.ldc = n;
+        }
+        double best_us = 1e300;
+        int best = -1;
+        for (int b = 0; b < F.lean_n; ++b) {
+            const int want = kclass == K_SPLIT2 ? 2 : kclass == K_SPLIT3 ? 3 : 0;
+            if (F.lean_pieces[b] != want) continue;
+            t_tls.force_body = b;
+            int variant = 0;
+            rc = build_table(gd->fam, d->cus, N, probs.data(), dtype, s.host, 1, &variant, 0);
+            if (rc != GEMM_OK) {
+                cleanup();
+                return rc;
+            }
+            const size_t bytes = table_bytes(((const GHeader *)s.host)->count);
+            std::vector<float> ms;
+            for (int r = 0; r < reps + 1; ++r) {
+                (void)hipEventRecord(e0, st);
+                rc = launch_table(gd, s, fam, 1, gd->grid[fam][1], bytes, st);
+                (void)hipEventRecord(e1, st);
+                if (rc != GEMM_OK || (e = hipEventSynchronize(e1)) != hipSuccess) {
+                    if (rc == GEMM_OK) {
+                        t_tls.hip_err = (int)e;
+                        rc = GEMM_E_HIP;
+                    }
+                    cleanup();
+                    return rc;
+                }
+                float t = 0;
+                (void)hipEventElapsedTime(&t, e0, e1);
+                if (r > 0) ms.push_back(t);
+            }
+            std::sort(ms.begin(), ms.end());
+            const double us = 1e3 * ms[ms.size() / 2] / double(N);   // per problem
+            if (us < best_us) {
+                best_us = us;
+                best = b;
+            }
+        }
+        if (best >= 0)
+            set_table_entry(TuneKey{kclass, kGroupedTrans, bucket(m), bucket(n), bucket(k)},
+                            TuneVal{best, 0, 8, best_us});
+    }
+    cleanup();
+    rebuild_lut();
+    if (out_path && *out_path) return save_table(out_path);
+    return GEMM_OK;
 }
 
 void gemm_grouped_slot_destroy(void *slot)

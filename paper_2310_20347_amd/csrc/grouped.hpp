@@ -117,23 +117,44 @@ struct FullBodies {
     }
 };
 
-// Lean bodies: 'N','N' operands with vectorised staging only, one shape
-// (plus, for the split family, the six-term shape): a few thousand
-// instructions instead of tens of thousands, so the persistent loop runs from
-// the instruction cache.  Body 0 -> SA, body 1 -> SB.
-template <class SA, class SB, int MINB_>
+// Lean bodies: 'N','N' operands with vectorised staging only, a few tile
+// shapes of one family (direct-staged, or split at read for the split
+// family), chosen per problem: a few thousand instructions per body instead
+// of tens of thousands, so the persistent loop runs from the instruction
+// cache.  Body b -> the b-th shape.
+template <int I, class S0, class... R>
+__device__ __forceinline__ void lean_dispatch(int body, const GemmArgs &p, int tm, int tn, char *lds)
+{
+    if constexpr (sizeof...(R) == 0) {
+        S0::run(p, tm, tn, lds);
+    } else {
+        if (body == I) {
+            S0::run(p, tm, tn, lds);
+            return;
+        }
+        lean_dispatch<I + 1, R...>(body, p, tm, tn, lds);
+    }
+}
+
+template <class S>
+constexpr int pieces_of()
+{
+    if constexpr (S::dt::SPLIT) return S::dt::PLANES;
+    else return 0;
+}
+
+constexpr int cmaxv(int a) { return a; }
+template <class... R>
+constexpr int cmaxv(int a, int b, R... r) { return cmaxv(a > b ? a : b, r...); }
+
+template <int MINB_, class... S>
 struct LeanBodies {
-    static constexpr int LDS = cmax(SA::lds, SB::lds);
+    static constexpr int N = sizeof...(S);
+    static constexpr int LDS = cmaxv(S::lds...);
     static constexpr int MINB = MINB_;
     static __device__ __forceinline__ void run(int body, const GemmArgs &p, int tm, int tn, char *lds)
     {
-        if constexpr (SB::lds > 0) {
-            if (body == 1) {
-                SB::run(p, tm, tn, lds);
-                return;
-            }
-        }
-        SA::run(p, tm, tn, lds);
+        lean_dispatch<0, S...>(body, p, tm, tn, lds);
     }
 };
 
@@ -200,15 +221,38 @@ __global__ void __launch_bounds__(256, BODIES::MINB) grouped_kernel(const char *
 }
 
 // What the host needs to know about one family's kernels.
+constexpr int kMaxLean = 8;
 struct GroupedFamily {
     const void *func = nullptr;       // all bodies
     int nshapes = 0;
     int mc[3] = {0, 0, 0}, nc[3] = {0, 0, 0};
     const void *lean = nullptr;       // 'N','N', aligned operands only
-    int lean_mc[2] = {0, 0}, lean_nc[2] = {0, 0};
+    int lean_n = 0;                   // lean bodies
+    int lean_mc[kMaxLean] = {}, lean_nc[kMaxLean] = {};
+    int lean_pieces[kMaxLean] = {};   // split family: bf16 pieces (2: x3, 3: x6); else 0
 };
 
-template <class S0, class S1, class S2, int MINB, class LA, class LB, int LMINB>
+template <class... S>
+void lean_shapes(GroupedFamily &f)
+{
+    const int mc[] = {S::mc...}, nc[] = {S::nc...}, pc[] = {pieces_of<S>()...};
+    static_assert(sizeof...(S) <= kMaxLean, "lean body count");
+    f.lean_n = (int)sizeof...(S);
+    for (int i = 0; i < f.lean_n; ++i) {
+        f.lean_mc[i] = mc[i];
+        f.lean_nc[i] = nc[i];
+        f.lean_pieces[i] = pc[i];
+    }
+}
+
+template <class LEAN>
+struct LeanOf;
+template <int MINB, class... S>
+struct LeanOf<LeanBodies<MINB, S...>> {
+    static void fill(GroupedFamily &f) { lean_shapes<S...>(f); }
+};
+
+template <class S0, class S1, class S2, int MINB, class LEAN>
 GroupedFamily make_family()
 {
     GroupedFamily f;
@@ -223,13 +267,8 @@ GroupedFamily make_family()
         f.nc[2] = S2::nc;
         f.nshapes = 3;
     }
-    f.lean = (const void *)&grouped_kernel<LeanBodies<LA, LB, LMINB>>;
-    f.lean_mc[0] = LA::mc;
-    f.lean_nc[0] = LA::nc;
-    if constexpr (LB::lds > 0) {
-        f.lean_mc[1] = LB::mc;
-        f.lean_nc[1] = LB::nc;
-    }
+    f.lean = (const void *)&grouped_kernel<LEAN>;
+    LeanOf<LEAN>::fill(f);
     return f;
 }
 

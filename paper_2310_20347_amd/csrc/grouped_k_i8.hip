@@ -1,14 +1,16 @@
-// Grouped persistent kernels of the i8 family (see grouped.hpp).
-// Full kernel: shape 0 is a 64x64 tile with element-wise variants for
-// unaligned operands, shape 1 a 128x64 tile; all four
-// transpositions.  Lean kernel: one 128x128 'N','N' body, direct-staged
-// (global -> LDS loads into a two-stage ring).
+// Grouped persistent kernels of the i8 family (see grouped.hpp). Full kernel:
+// shape 0 is a 64x64 tile with element-wise variants for unaligned operands,
+// shape 1 a 128x64 tile; all four transpositions. Lean kernel ('N','N',
+// aligned operands; the body is chosen per problem): direct-staged 128x128,
+// 64x128, 32x128 and 256x128 (64-byte stages; an 8-bit B panel is stored
+// n-contiguous, so its tile is at least 128 wide).
 #include "grouped.hpp"
 
 namespace mg {
 GroupedFamily grouped_family_i8()
 {
     return make_family<Shape<TI8, 64, 64, 2>, Shape<TI8, 128, 64, 2>, NoShape, 1,
-                       DShape<TI8, 128, 128, 2>, NoShape, 2>();
+                       LeanBodies<2, DShape<TI8, 128, 128, 2>, DShape<TI8, 64, 128, 2>,
+                                  DShape<TI8, 32, 128, 2>, DShape<TI8, 256, 128, 2, 64>>>();
 }
 }  // namespace mg

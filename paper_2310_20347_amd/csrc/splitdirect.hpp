@@ -56,14 +56,10 @@ struct SDTile {
     {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            float x0 = v[2 * q], x1 = v[2 * q + 1];
+            u32 w[P];
+            split_pair<P>(v[2 * q], v[2 * q + 1], w);
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const u32 h0 = bf16_bits(x0), h1 = bf16_bits(x1);
-                pc[p][q] = h0 | (h1 << 16);
-                x0 -= bf16_val(h0);
-                x1 -= bf16_val(h1);
-            }
+            for (int p = 0; p < P; ++p) pc[p][q] = w[p];
         }
     }
 

@@ -19,9 +19,6 @@
 #include "abi_internal.hpp"
 #include "mgemm.h"
 
-namespace mg {
-void launch_fill(void *p, int64_t count, int kind, uint32_t seed, hipStream_t s);
-}
 
 using namespace mg;
 

@@ -8,6 +8,10 @@ plus the benchmark workloads' own shapes.
 
     python -m paper_2310_20347_amd.tune [--quick] [--out PATH] [--model-keep N]
     python -m paper_2310_20347_amd.tune --model-check [--dtypes 0,1,2]
+    python -m paper_2310_20347_amd.tune --grouped [--dtypes 1,5] [--out PATH]
+
+--grouped tunes the grouped kernel's tile body per size bucket instead
+(gemm_tune_grouped: a batch of identical problems per bucket, every body).
 """
 import argparse
 import itertools
@@ -49,6 +53,8 @@ def main():
     p.add_argument("--dtypes", default="0,1,2,3,4,5,7,8")
     p.add_argument("--model-keep", type=int, default=0,
                    help="time only the analytical model's first N configurations per shape")
+    p.add_argument("--grouped", action="store_true",
+                   help="tune the grouped kernel's body per size bucket (m, n, k in 16..4096)")
     p.add_argument("--model-check", action="store_true",
                    help="measure the analytical model instead of tuning: time every "
                         "configuration on a sample of shapes and report how much slower the "
@@ -59,6 +65,18 @@ def main():
     mg.gemm_init(None)
     if a.model_check:
         return model_check([int(x) for x in a.dtypes.split(",")], a.reps, torch)
+    if a.grouped:
+        grid = [2 ** e for e in range(4, 13)]
+        shapes = list(itertools.product(grid, grid, grid))
+        dts = [int(x) for x in a.dtypes.split(",")] if a.dtypes != p.get_default("dtypes") \
+            else [mg.GEMM_F32_BF16X3, mg.GEMM_I8]
+        for dt in dts:
+            t0 = time.time()
+            mg.gemm_tune_grouped(dt, shapes, reps=a.reps, out_path=a.out)
+            print(f"tuned grouped {mg.DTYPE_NAMES[dt]}: {len(shapes)} buckets in "
+                  f"{time.time() - t0:.1f} s", flush=True)
+        print(f"wrote {a.out}")
+        return 0
     for dt in [int(x) for x in a.dtypes.split(",")]:
         shapes = shapes_for(dt, a.quick)
         t0 = time.time()
