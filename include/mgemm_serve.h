@@ -62,6 +62,10 @@ typedef struct {
                                /* counts from its release.  Serving a set of requests     */
                                /* this way gives each one's alone-latency (on an          */
                                /* otherwise idle GPU, same path and overheads).           */
+    int graph_replay;          /* step loop: 1 = each step's grouped launch of a dtype is  */
+                               /* the replay of a HIP graph captured once per launch slot  */
+                               /* (the slot's table copy and persistent kernel), 0 =       */
+                               /* direct launches.  The queue mode ignores it.            */
 } serve_config;
 
 typedef struct {

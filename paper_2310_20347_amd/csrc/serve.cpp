@@ -168,6 +168,10 @@ public:
                 if (rc != GEMM_OK) return rc;
                 if ((e = hipEventCreateWithFlags(&ev_[d][s], hipEventDisableTiming)) != hipSuccess)
                     return fail(e);
+                if (cfg.graph_replay && gemm_grouped_num_bodies(d) > 0) {
+                    rc = capture(d, s);
+                    if (rc != GEMM_OK) return rc;
+                }
             }
         }
         // arrivals count from here: the arena and slot set-up (hundreds of
@@ -181,6 +185,8 @@ public:
         (void)hipDeviceSynchronize();
         for (int d = 0; d < GEMM_NUM_DTYPES; ++d) {
             for (int s = 0; s < slots_per_dtype_; ++s) {
+                if (exec_[d][s]) (void)hipGraphExecDestroy(exec_[d][s]);
+                exec_[d][s] = nullptr;
                 if (slot_[d][s]) gemm_grouped_slot_destroy(slot_[d][s]);
                 if (ev_[d][s]) (void)hipEventDestroy(ev_[d][s]);
                 slot_[d][s] = nullptr;
@@ -213,11 +219,17 @@ public:
         void *slot = slot_[l.dtype][l.slot];
         int rc = gemm_grouped_slot_write(slot, (int64_t)probs.size(), probs.data(), l.dtype);
         if (rc != GEMM_OK) return rc;
-        hipStream_t saved = t_tls.stream;
-        t_tls.stream = stream_[l.dtype];
-        rc = gemm_grouped_slot_launch(slot);
-        t_tls.stream = saved;
-        if (rc != GEMM_OK) return rc;
+        if (hipGraphExec_t g = exec_[l.dtype][l.slot]) {
+            // the captured copy re-reads the slot's pinned table just written
+            hipError_t e = hipGraphLaunch(g, stream_[l.dtype]);
+            if (e != hipSuccess) return fail(e);
+        } else {
+            hipStream_t saved = t_tls.stream;
+            t_tls.stream = stream_[l.dtype];
+            rc = gemm_grouped_slot_launch(slot);
+            t_tls.stream = saved;
+            if (rc != GEMM_OK) return rc;
+        }
         hipError_t e = hipEventRecord(ev_[l.dtype][l.slot], stream_[l.dtype]);
         return e == hipSuccess ? GEMM_OK : fail(e);
     }
@@ -243,11 +255,42 @@ private:
         t_tls.hip_err = (int)e;
         return GEMM_E_HIP;
     }
+    // Captures slot s of dtype d's launch (table copy + persistent kernel) on
+    // the dtype's stream into a graph.  The slot is first written with a
+    // one-problem 'N','N' table of the dtype, which fixes its kernel (the
+    // compact one: arena operands are aligned, as every request's are).
+    int capture(int d, int s)
+    {
+        gemm_problem q;
+        std::memset(&q, 0, sizeof q);
+        q.transA = q.transB = 'N';
+        q.m = q.n = q.k = 16;
+        q.alpha = 1.0;
+        q.A = q.B = q.C = base_;
+        q.lda = q.ldb = q.ldc = 16;
+        int rc = gemm_grouped_slot_write(slot_[d][s], 1, &q, d);
+        if (rc != GEMM_OK) return rc;
+        hipStream_t st = stream_[d];
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return fail(e);
+        hipStream_t saved = t_tls.stream;
+        t_tls.stream = st;
+        rc = gemm_grouped_slot_launch(slot_[d][s]);
+        t_tls.stream = saved;
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(st, &g);
+        if (rc == GEMM_OK && e == hipSuccess)
+            e = hipGraphInstantiate(&exec_[d][s], g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (rc != GEMM_OK) return rc;
+        return e == hipSuccess ? GEMM_OK : fail(e);
+    }
     std::chrono::steady_clock::time_point t0_;
     char *base_ = nullptr;
     hipStream_t stream_[GEMM_NUM_DTYPES] = {};
     void *slot_[GEMM_NUM_DTYPES][4] = {};
     hipEvent_t ev_[GEMM_NUM_DTYPES][4] = {};
+    hipGraphExec_t exec_[GEMM_NUM_DTYPES][4] = {};
     int slots_per_dtype_ = 0;
 };
 
@@ -326,7 +369,8 @@ int check_config(const serve_config *cfg)
     if (cfg->budget_bytes <= 0 || cfg->max_active < 1 || cfg->max_active > 8192 ||
         cfg->step_tile_budget < 1 || cfg->request_tile_cap < 1 || cfg->inflight_steps < 1 ||
         cfg->inflight_steps > 4 || !(cfg->watchdog_s > 0) || cfg->warmup_requests < 0 ||
-        (cfg->closed_loop != 0 && cfg->closed_loop != 1))
+        (cfg->closed_loop != 0 && cfg->closed_loop != 1) ||
+        (cfg->graph_replay != 0 && cfg->graph_replay != 1))
         return -1;
     return 0;
 }

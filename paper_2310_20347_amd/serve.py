@@ -20,7 +20,7 @@ class Request(ctypes.Structure):
 class Config(ctypes.Structure):
     _fields_ = [("budget_bytes", _I64), ("max_active", _INT), ("step_tile_budget", _I64),
                 ("request_tile_cap", _I64), ("inflight_steps", _INT), ("watchdog_s", _D),
-                ("warmup_requests", _I64), ("closed_loop", _INT)]
+                ("warmup_requests", _I64), ("closed_loop", _INT), ("graph_replay", _INT)]
 
 
 class Stats(ctypes.Structure):
@@ -90,15 +90,17 @@ def serve_layout(m: int, n: int, k: int, dtype: int):
 
 
 def config(budget_bytes=64 << 30, max_active=512, step_tile_budget=4096, request_tile_cap=512,
-           inflight_steps=1, watchdog_s=10.0, warmup_requests=0, closed_loop=0) -> Config:
+           inflight_steps=1, watchdog_s=10.0, warmup_requests=0, closed_loop=0,
+           graph_replay=1) -> Config:
     """Serving configuration.  One step in flight per dtype stream by default:
     requests that arrive during a step join the next one instead of queueing
     behind a second launch on the same stream (measured at 20k req/s: p99
     0.5 ms with one in flight, 6.8 ms with two).  closed_loop=1 serves one
     request at a time (each released when the previous completes, latency
-    from the release): the requests' alone-latencies."""
+    from the release): the requests' alone-latencies.  graph_replay=1 replays
+    a captured HIP graph per launch slot instead of launching directly."""
     return Config(budget_bytes, max_active, step_tile_budget, request_tile_cap, inflight_steps,
-                  watchdog_s, warmup_requests, closed_loop)
+                  watchdog_s, warmup_requests, closed_loop, graph_replay)
 
 
 def _requests(reqs: Sequence[Any]):
