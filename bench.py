@@ -39,6 +39,8 @@ def parse():
                    help="only the timed steps (for rocprofv3 runs)")
     p.add_argument("--profile-precision", action="store_true",
                    help="only the 8192^3 GEMM of every precision path (for rocprofv3 runs)")
+    p.add_argument("--profile-grouped", action="store_true",
+                   help="only the 512-GEMM grouped launches, split x3 and INT8 (for rocprofv3 runs)")
     p.add_argument("--calib-copy", action="store_true",
                    help="copy a 1 GiB buffer once before the steps: a kernel of known HBM "
                         "traffic to scale rocprofv3's FETCH_SIZE / WRITE_SIZE counters")
@@ -94,11 +96,29 @@ def cpu_baseline(target_s=20.0):
         t += time.perf_counter() - t0
         flops += 2.0 * rows * n * k
         rows_used.append(rows)
-    return {"value": flops / t / 1e12, "unit": "TFLOP/s", "cores": oracle.threads(),
+    cores = oracle.threads()
+    # one thread on 1/(4 cores) of each band (the rate does not depend on
+    # m): about a quarter of the all-core run's time
+    oracle.set_threads(1)
+    f1 = t1 = 0.0
+    try:
+        for i, (m, n, k) in enumerate(SWEEP):
+            rows = max(1, rows_used[i] // (4 * max(1, cores)))
+            a = inputs.uniform((rows, k), 100 + i)
+            b = inputs.uniform((k, n), 200 + i)
+            t0 = time.perf_counter()
+            oracle.gemm_f64("N", "N", rows, n, k, 1.0, a, k, b, n)
+            t1 += time.perf_counter() - t0
+            f1 += 2.0 * rows * n * k
+    finally:
+        oracle.set_threads(cores)
+    return {"value": flops / t / 1e12, "unit": "TFLOP/s", "cores": cores,
             "kind": "oracle",
             "sample": ("FP64 oracle on a band of rows of C for each sweep shape (all columns, "
                        f"full k; rows per shape {rows_used}), {flops / 1e9:.1f} GFLOP in "
-                       f"{t:.1f} s")}
+                       f"{t:.1f} s"),
+            "single_thread": {"value": f1 / t1 / 1e12, "unit": "TFLOP/s", "cores": 1,
+                              "sample": f"the same bands cut to {f1 / 1e9:.1f} GFLOP, {t1:.1f} s"}}
 
 
 def main():
@@ -116,6 +136,14 @@ def main():
     stream = torch.cuda.current_stream()
     if args.profile_precision:
         print(json.dumps({"precision_8192": precision_8192(mg, torch, stream)}), flush=True)
+        return
+    if args.profile_grouped:
+        if args.calib_copy:
+            src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+            torch.empty_like(src).copy_(src)
+            torch.cuda.synchronize()
+            del src
+        print(json.dumps({"grouped": grouped_bench(mg, torch, stream, reps=3)}), flush=True)
         return
 
     # operands, resident in HBM before timing
@@ -193,6 +221,9 @@ def main():
         out["serving"] = serving_bench(mg, torch)
     if not args.profile_only and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
+    # the per-precision 8192^3 results go last on the line
+    if "paths" in out and "precision_8192" in out["paths"]:
+        out["precision_8192"] = out["paths"].pop("precision_8192")
     print(json.dumps(out), flush=True)
 
 
@@ -367,7 +398,39 @@ def precision_8192(mg, torch, stream):
                                     stream=stream), torch, stream)
     prec["i8"] = {"ms": round(ms, 3), "tops": round(2.0 * n ** 3 / ms / 1e9, 1),
                   "mfma_util": round(2.0 * n ** 3 / ms / 1e9 / 5033.0, 4)}
+    del ai, bi
+    prec.update(integer_paths(mg, torch, stream, Ci))
     return prec
+
+
+def integer_paths(mg, torch, stream, C):
+    """INT16 / INT32 GEMM at 8192^3 through the tuned dispatch (INT8 MFMA
+    digit products: 4 / 10 INT8 products per product), with the INT8 MFMA
+    work they run as a fraction of its peak; and at 4096^3 both
+    configurations: the digit products against the vector-ALU tile."""
+    out = {}
+    for name, dt, tdt, products in (("i16", mg.GEMM_I16, torch.int16, 4),
+                                    ("i32", mg.GEMM_I32, torch.int32, 10)):
+        lim = 2 ** 15 if tdt == torch.int16 else 2 ** 31
+        g = torch.Generator(device="cuda")
+        g.manual_seed(43)
+        for n, cfgs in ((8192, (None,)), (4096, (1, 0))):
+            A = torch.randint(-lim, lim, (n, n), generator=g, device="cuda", dtype=torch.int64).to(tdt)
+            B = torch.randint(-lim, lim, (n, n), generator=g, device="cuda", dtype=torch.int64).to(tdt)
+            Cv = C if n == C.shape[0] else C.view(-1)[:n * n].view(n, n)
+            for cfg in cfgs:
+                if cfg is not None:
+                    mg.force_config(dt, cfg, 0)
+                ms = _time_call(lambda: mg.gemm("N", "N", n, n, n, 1, A, n, B, n, 0, Cv, n, dt,
+                                                stream=stream), torch, stream, reps=3)
+                used = mg.last_config()["cfg"]
+                mg.force_config(dt, -1, 0)
+                tops = 2.0 * n ** 3 / ms / 1e9
+                key = name if cfg is None else f"{name}_{n}_{'digits' if cfg == 1 else 'valu'}"
+                out[key] = {"ms": round(ms, 3), "tops": round(tops, 1), "cfg": used,
+                            "int8_mfma_util": round(products * tops / 5033.0, 4) if used == 1 else None}
+            del A, B
+    return out
 
 
 def packing_configs(mg, torch, stream):

@@ -57,6 +57,8 @@ def _load():
         _build.build()
     lib = ctypes.CDLL(_LIB_PATH)
     lib.oracle_threads.restype = _INT
+    lib.oracle_set_threads.argtypes = [_INT]
+    lib.oracle_set_threads.restype = None
     lib.oracle_gemm_f64.argtypes = [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64,
                                     _D, _P, _I64, _P, _I64]
     lib.oracle_gemm_entries_f64.argtypes = [_C, _C, _I64, _D, _P, _I64, _P, _I64, _D,
@@ -86,6 +88,11 @@ def _load():
         getattr(lib, f).restype = None
     _lib = lib
     return lib
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's following calls (n >= 1)."""
+    _load().oracle_set_threads(int(n))
 
 
 def threads() -> int:

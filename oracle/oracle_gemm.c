@@ -40,6 +40,15 @@
 
 static int is_t(char t) { return t == 'T' || t == 't' || t == 'C' || t == 'c'; }
 
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int oracle_threads(void)
 {
 #ifdef _OPENMP
