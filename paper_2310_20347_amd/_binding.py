@@ -45,7 +45,9 @@ class MGemmError(RuntimeError):
 
 
 def lib_path() -> str:
-    return os.path.join(_HERE, "libmgemm.so")
+    """The in-tree library, or the build named by MGEMM_LIBRARY (the
+    sanitizer build of the host code uses this)."""
+    return os.environ.get("MGEMM_LIBRARY") or os.path.join(_HERE, "libmgemm.so")
 
 
 _lib = None

@@ -3,6 +3,12 @@
 Every source under csrc/ is compiled in parallel to an object file, then
 linked into paper_2310_20347_amd/libmgemm.so.  All device code is compiled
 with packed-FP32 instructions disabled.
+
+build_sanitized() makes a second library, _build_san/libmgemm_san.so, whose
+host code (the C ABI, dispatch, tuning table, serving loop, model: the .cpp
+sources) is compiled with AddressSanitizer and UndefinedBehaviorSanitizer
+(host side only; the kernels' objects are the normal build's).  Load it with
+MGEMM_LIBRARY and the sanitizer runtime preloaded (sanitizer_env()).
 """
 import concurrent.futures as cf
 import glob
@@ -54,5 +60,65 @@ def build(verbose=False, jobs=None):
     return OUT
 
 
+SAN_DIR = os.path.join(HERE, "_build_san")
+SAN_OUT = os.path.join(SAN_DIR, "libmgemm_san.so")
+SAN_FLAGS = ["-O1", "-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def sanitizer_runtime():
+    """The compiler's AddressSanitizer runtime (preloaded into the test process)."""
+    rt = glob.glob(os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(HIPCC))),
+                                "llvm", "lib", "clang", "*", "lib", "linux",
+                                "libclang_rt.asan-x86_64.so"))
+    if not rt:
+        rt = glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so")
+    return rt[0] if rt else None
+
+
+def sanitizer_env():
+    env = dict(os.environ)
+    env["MGEMM_LIBRARY"] = SAN_OUT
+    env["LD_PRELOAD"] = sanitizer_runtime() or ""
+    env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=1"
+    env["UBSAN_OPTIONS"] = "halt_on_error=1:print_stacktrace=1"
+    return env
+
+
+def build_sanitized(verbose=False, jobs=None):
+    """The host sources with ASan/UBSan, linked with the normal build's
+    kernel objects (build() first)."""
+    os.makedirs(SAN_DIR, exist_ok=True)
+    cpp = sorted(glob.glob(os.path.join(CSRC, "*.cpp")))
+    hip = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+    def comp(src):
+        obj = os.path.join(SAN_DIR, os.path.basename(src) + ".o")
+        cmd = [HIPCC] + [f for f in COMMON if f != "-O3"] + SAN_FLAGS + ["-x", "hip", "-c", src,
+                                                                        "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr[-4000:]}")
+        return obj
+
+    with cf.ThreadPoolExecutor(jobs or min(8, os.cpu_count() or 4)) as ex:
+        objs = list(ex.map(comp, cpp))
+    objs += [os.path.join(BUILD, os.path.basename(s) + ".o") for s in hip]
+    missing = [o for o in objs if not os.path.exists(o)]
+    if missing:
+        raise RuntimeError(f"run build() first: missing {missing[:3]}")
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined", "-shared-libsan", "-o", SAN_OUT] + objs + ["-ldl"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return SAN_OUT
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--sanitize" in sys.argv:
+        print(build_sanitized(verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))
