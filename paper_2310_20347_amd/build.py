@@ -29,10 +29,18 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", CSRC, "-
           "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
 
 
+# Per-source flags.  The grouped persistent kernels claim their next tile
+# with an atomic whose result is used only after the current tile; the
+# compiler's atomic optimizer (which combines a wave's atomics) would wait for
+# that result right after issuing it, at the start of every tile.
+EXTRA = {"grouped_k_": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+
+
 def _compile(src, verbose):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     lang = ["-x", "hip"] if src.endswith(".cpp") else []
-    cmd = [HIPCC] + COMMON + lang + ["-c", src, "-o", obj]
+    extra = [f for k, v in EXTRA.items() if os.path.basename(src).startswith(k) for f in v]
+    cmd = [HIPCC] + COMMON + extra + lang + ["-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
