@@ -5,9 +5,10 @@
 // search over the tile prefix, maps the local id through that problem's
 // raster order and runs the tile body (the same C-resident tile as the
 // single-GEMM kernel).  Tile ids beyond each workgroup's first come from
-// atomic counters (one per XCD group); the last workgroup to finish resets
-// the counters to zero, so a launch leaves them ready for the next one (no
-// memset node is needed, which keeps the launch capturable in a graph).
+// atomic counters (one per XCD group), each claimed at the start of the tile
+// before it; the last workgroup to finish resets the counters to zero, so a
+// launch leaves them ready for the next one (no memset node is needed, which
+// keeps the launch capturable in a graph).
 #pragma once
 
 #include "direct.hpp"
@@ -168,12 +169,16 @@ struct LeanBodies {
 // counters[8] counts finished workgroups.
 constexpr int kChunk = 64;
 constexpr int kGroups = 8;
+// The prefix array of tables of up to kLdsPrefix problems is copied to LDS at
+// the start, so each tile's problem search reads LDS instead of memory.
+constexpr int kLdsPrefix = 1024;
 
 template <class BODIES>
-__global__ void __launch_bounds__(256, BODIES::MINB) grouped_kernel(const char *table, int *counters)
+__global__ void __launch_bounds__(256, BODIES::MINB) grouped_kernel(const char *__restrict__ table, int *counters)
 {
     __shared__ __attribute__((aligned(16))) char lds[BODIES::LDS];
     __shared__ int s_next;
+    __shared__ int s_ts[kLdsPrefix];
     const GHeader *h = (const GHeader *)table;
     const GDesc *descs = (const GDesc *)(table + sizeof(GHeader));
     const int total = h->total_tiles, count = h->count;
@@ -184,17 +189,26 @@ __global__ void __launch_bounds__(256, BODIES::MINB) grouped_kernel(const char *
     const int members = ((int)gridDim.x - g + L - 1) / L;   // workgroups of group g
     // position v of group g -> global tile id
     auto tile_of = [&](int v) { return ((v / kChunk) * L + g) * kChunk + v % kChunk; };
+    const bool in_lds = count <= kLdsPrefix;
+    if (in_lds) {
+        for (int i = threadIdx.x; i < count; i += blockDim.x) s_ts[i] = ts[i];
+        __syncthreads();
+    }
+    const int *pre = in_lds ? (const int *)s_ts : ts;
     int t = tile_of((int)blockIdx.x / L);
-    // the next tile id is fetched while the current tile is computed
-    if (threadIdx.x == 0 && t < total) s_next = tile_of(members + atomicAdd(&counters[g], 1));
     while (t < total) {
+        // claim the next tile now and use the claim after this tile: the
+        // atomic's round trip overlaps the tile instead of delaying its start
+        int claim = 0;
+        if (threadIdx.x == 0) claim = atomicAdd(&counters[g], 1);
         // last problem whose first tile is <= t: 64-way search per wave over
-        // the compact prefix array, two dependent loads for up to 4096 problems
+        // the compact prefix array (in LDS, or two dependent loads for up to
+        // 4096 problems)
         int lo = 0, hi = count;
         while (hi - lo > 1) {
             const int step = (hi - lo + 63) >> 6;
             const int i = lo + lane * step;
-            const bool le = i < hi && ts[i] <= t;
+            const bool le = i < hi && pre[i] <= t;
             const unsigned long long mask = __ballot(le);
             const int last = 63 - __builtin_clzll(mask);   // lane 0 always qualifies
             lo = lo + last * step;
@@ -204,12 +218,12 @@ __global__ void __launch_bounds__(256, BODIES::MINB) grouped_kernel(const char *
         const GemmArgs p = descs[lo].a;
         const int body = descs[lo].body;
         int tm, tn;
-        raster(t - ts[lo], p.tiles_m, p.tiles_n, p.order, p.group, tm, tn);
+        raster(t - pre[lo], p.tiles_m, p.tiles_n, p.order, p.group, tm, tn);
         BODIES::run(body, p, tm, tn, lds);
+        if (threadIdx.x == 0) s_next = tile_of(members + claim);
         __syncthreads();
         t = __builtin_amdgcn_readfirstlane(s_next);
         __syncthreads();
-        if (threadIdx.x == 0 && t < total) s_next = tile_of(members + atomicAdd(&counters[g], 1));
     }
     if (threadIdx.x == 0) {
         __threadfence();

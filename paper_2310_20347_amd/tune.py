@@ -51,6 +51,10 @@ def main():
     p.add_argument("--reps", type=int, default=5)
     p.add_argument("--out", default=os.path.join(HERE, "mgemm_tune.json"))
     p.add_argument("--dtypes", default="0,1,2,3,4,5,7,8")
+    p.add_argument("--layouts", default="NN,NT,TN,TT",
+                   help="layouts to tune (the table keeps the entries of the others)")
+    p.add_argument("--chunk", type=int, default=16,
+                   help="shapes per tuner call (progress is printed after each)")
     p.add_argument("--model-keep", type=int, default=0,
                    help="time only the analytical model's first N configurations per shape")
     p.add_argument("--grouped", action="store_true",
@@ -77,12 +81,17 @@ def main():
                   f"{time.time() - t0:.1f} s", flush=True)
         print(f"wrote {a.out}")
         return 0
+    layouts = tuple(a.layouts.split(","))
     for dt in [int(x) for x in a.dtypes.split(",")]:
         shapes = shapes_for(dt, a.quick)
         t0 = time.time()
-        mg.gemm_tune(dt, shapes, reps=a.reps, out_path=a.out, model_keep=a.model_keep)
-        print(f"tuned {mg.DTYPE_NAMES[dt]}: {len(shapes)} shapes in {time.time() - t0:.1f} s",
-              flush=True)
+        for i in range(0, len(shapes), a.chunk):
+            mg.gemm_tune(dt, shapes[i:i + a.chunk], reps=a.reps, out_path=a.out,
+                         model_keep=a.model_keep, layouts=layouts)
+            print(f"  {mg.DTYPE_NAMES[dt]}: {min(i + a.chunk, len(shapes))}/{len(shapes)} shapes, "
+                  f"{time.time() - t0:.1f} s", flush=True)
+        print(f"tuned {mg.DTYPE_NAMES[dt]}: {len(shapes)} shapes x {len(layouts)} layouts in "
+              f"{time.time() - t0:.1f} s", flush=True)
     print(f"wrote {a.out}")
 
 

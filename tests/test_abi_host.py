@@ -227,19 +227,27 @@ def test_analytical_model_structure():
 def test_shipped_tuning_table_names_existing_configurations():
     """Configurations are only ever appended to a class, so the shipped table
     keeps naming the tiles it was tuned on: every entry's configuration exists
-    in its class and has an 'N','N' kernel (the layout the tuner times)."""
+    in its class and has a kernel for the entry's layout (trans = 2 tA + tB);
+    grouped entries (trans 4) name one of the family's grouped bodies."""
     import json
     path = os.path.join(os.path.dirname(os.path.abspath(mg.__file__)), "mgemm_tune.json")
     table = json.load(open(path))
     assert table["arch"].startswith("gfx950")
     family = {0: mg.GEMM_F32, 1: mg.GEMM_F32_BF16X3_ONLY, 2: mg.GEMM_F32_BF16X6, 3: mg.GEMM_BF16,
-              4: mg.GEMM_F16, 5: mg.GEMM_F8E4M3, 6: mg.GEMM_I8, 7: mg.GEMM_F64}
-    seen = set()
+              4: mg.GEMM_F16, 5: mg.GEMM_F8E4M3, 6: mg.GEMM_I8, 7: mg.GEMM_F64,
+              8: mg.GEMM_I16, 9: mg.GEMM_I32}
+    layouts = {0: ("N", "N"), 1: ("N", "T"), 2: ("T", "N"), 3: ("T", "T")}
+    seen, grouped = set(), set()
     for e in table["entries"]:
         dt = family[e["kclass"]]
-        assert 0 <= e["cfg"] < mg.num_configs(dt), e
-        assert mg.config_supports(dt, e["cfg"], "N", "N"), e
+        if e["trans"] == 4:
+            assert 0 <= e["cfg"] < len(mg.grouped_bodies_info(dt)), e
+            grouped.add(e["kclass"])
+        else:
+            assert 0 <= e["cfg"] < mg.num_configs(dt), e
+            assert mg.config_supports(dt, e["cfg"], *layouts[e["trans"]]), e
+            seen.add((e["kclass"], e["trans"]))
         assert e["order"] in (0, 1) and e["group"] > 0 and e["us"] > 0, e
         assert all(4 <= e[b] <= 12 for b in ("bm", "bn", "bk")), e
-        seen.add(e["kclass"])
-    assert seen == set(family)
+    assert seen == {(kc, tr) for kc in family for tr in range(4)}
+    assert grouped >= {6}
