@@ -343,6 +343,10 @@ int gemm_last_hip_error(void);
  *     LDS), 4 = B not packed, 5 = neither packed (no LDS), 6 = digit planes
  *     (INT16 / INT32: a packing pass writes int8 digit planes, then INT8
  *     tiles); negative as gemm_config_info's errors.
+ *   gemm_config_mfma(dtype, id): the edge of the MFMA blocks its wave
+ *     tiles are made of: 16 (16x16 MFMAs) or 32 (32x32 MFMAs: BF16, FP16,
+ *     FP8 and INT8 direct-staged tiles, and the packed split tiles built on
+ *     the BF16 ones); negative as gemm_config_info's errors.
  *   gemm_config_layouts(dtype, id): bit (2*t + v) is set when the
  *     configuration has a kernel for trans index t = 2*(transA is T) +
  *     (transB is T) with vectorised (v = 1: 16-byte aligned operands and
@@ -357,6 +361,7 @@ int gemm_last_hip_error(void);
 int gemm_num_configs(int dtype);
 int gemm_config_info(int dtype, int id, int64_t out[8]);
 int gemm_config_staging(int dtype, int id);
+int gemm_config_mfma(int dtype, int id);
 int gemm_config_layouts(int dtype, int id);
 int gemm_force_config(int dtype, int id, int order);
 int gemm_last_config(int64_t out[4]);

@@ -119,6 +119,8 @@ def lib():
     L.gemm_config_info.restype = _INT
     L.gemm_config_staging.argtypes = [_INT, _INT]
     L.gemm_config_staging.restype = _INT
+    L.gemm_config_mfma.argtypes = [_INT, _INT]
+    L.gemm_config_mfma.restype = _INT
     L.gemm_config_layouts.argtypes = [_INT, _INT]
     L.gemm_config_layouts.restype = _INT
     L.gemm_force_config.argtypes = [_INT, _INT, _INT]
@@ -384,6 +386,7 @@ def config_info(dtype: int, cfg: int) -> dict:
                         "digit_planes")[st]
                        if st >= 0 else None)
     info["layouts"] = int(lib().gemm_config_layouts(int(dtype), int(cfg)))
+    info["mfma"] = int(lib().gemm_config_mfma(int(dtype), int(cfg)))
     return info
 
 

@@ -189,6 +189,9 @@ void ensure_registered()
     add_packed(nlate, g_cfgs.size());
     register_f64_late(g_cfgs);
     register_int_late(g_cfgs);
+    const size_t nw32 = g_cfgs.size();
+    register_direct_w32_late(g_cfgs);
+    add_packed(nw32, g_cfgs.size());
     for (size_t i = 0; i < g_cfgs.size(); ++i) g_by_class[g_cfgs[i].kclass].push_back((int)i);
     g_registered = true;
 }
@@ -956,6 +959,15 @@ int gemm_config_staging(int dtype, int id)
     if (c.kind == 7) return 6;
     if (c.unpacked) return 2 + c.unpacked;
     return c.packed >= 0 ? 2 : (c.direct ? 1 : 0);
+}
+
+int gemm_config_mfma(int dtype, int id)
+{
+    if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -1;
+    ensure_registered();
+    const std::vector<int> &ids = g_by_class[class_for_query(dtype)];
+    if (id < 0 || id >= (int)ids.size()) return -2;
+    return g_cfgs[ids[id]].mfma;
 }
 
 int gemm_config_layouts(int dtype, int id)

@@ -83,12 +83,33 @@ __device__ __forceinline__ void wait_vm()
 // Rows of 256 bytes or more start on a bank line, so the 128-byte half is
 // chunk bit 3 and the swizzle may flip it; 128-byte rows share a line with
 // their neighbour (row parity picks the half) and are spread within it.
+//   SK 66: 16-bit transposing read of the 32x32 MFMAs: the two 16-lane groups
+//          served together read the same 4 k rows (kr0 .. kr0+3), 64 bytes of
+//          each, so each row's 64 bytes take their own quarter of the bank
+//          line (rows of 256 bytes or more) or of the row's half line.
+//   SK 65: 8-bit transposing read of the 32x32 MFMAs: the pair reads 8 k rows
+//          of 32 bytes each, spread over the eighths of the bank line (or of
+//          the half line).
 template <int SK, int RB, int GS>
 __device__ __forceinline__ int mn_chunk(int kr, int lc)
 {
     static_assert((GS & (GS - 1)) == 0 && RB >= 128, "power-of-two group stride, rows >= 128 B");
     int x, mask = 7;
-    if constexpr (SK == 8) {
+    if constexpr (SK == 66) {
+        if constexpr (RB >= 256) {
+            x = 4 * (kr & 3);
+            mask = 15;
+        } else {
+            x = 4 * ((kr >> 1) & 1);
+        }
+    } else if constexpr (SK == 65) {
+        if constexpr (RB >= 256) {
+            x = 2 * (kr & 7);
+            mask = 15;
+        } else {
+            x = 2 * ((kr >> 1) & 3);
+        }
+    } else if constexpr (SK == 8) {
         x = 4 * ((kr >> 3) & 1);
     } else if constexpr (SK == 4) {
         x = 4 * ((kr >> 2) & 1);
@@ -127,19 +148,25 @@ __device__ __forceinline__ int mn_off(int kr, int byte)
 //     groups' chunks fill the half line exactly once.
 //   KB 64: four rows per line, rows r and r+4 share a quarter line; their
 //     swizzles differ by 3, so {c, c^3, c^1, c^2} (or c^2, c^1) are distinct.
-template <int KB>
+//   R32 (the 32x32 MFMAs' fragments, KB 128): a pass reads rows r0 .. r0+7
+//     and r0+16 .. r0+23 at the same logical chunk; rows 16 apart share a
+//     half line, so bit 4 of the row flips the set ({0, 3, 5, 6} <-> {1, 2,
+//     4, 7}).  Passes of the 16-row pattern read 8 rows that agree in bit 4,
+//     so they stay conflict-free.
+template <int KB, bool R32 = false>
 __device__ __forceinline__ int kslot(int r, int lc)
 {
+    static_assert(!R32 || KB == 128, "32-row fragments use 128-byte rows");
     if constexpr (KB == 128)
-        return lc ^ ((r & 7) ^ (((r >> 1) ^ (r >> 2)) & 1));
+        return lc ^ ((r & 7) ^ (((r >> 1) ^ (r >> 2)) & 1)) ^ (R32 ? ((r >> 4) & 1) : 0);
     else
         return lc ^ (3 * ((r >> 2) & 1));
 }
 
-template <int KB>
+template <int KB, bool R32 = false>
 __device__ __forceinline__ int k_off(int row, int byte)
 {
-    return row * KB + (kslot<KB>(row, byte >> 4) << 4) + (byte & 15);
+    return row * KB + (kslot<KB, R32>(row, byte >> 4) << 4) + (byte & 15);
 }
 
 // Fragment of the 16-row block at panel row r0 and chunk c of a k-contiguous
@@ -158,12 +185,29 @@ __device__ __forceinline__ void read_frag_k(const char *panel, int r0, int c, in
     }
 }
 
+// Fragment of the 32-row block at panel row r0 and MFMA chunk c of a
+// k-contiguous panel, for the 32x32 MFMAs: lane l holds row r0 + l%32 and
+// the FDW*4 bytes of k that start at chunk c's lane half l/32.
+template <class DT, int KB>
+__device__ __forceinline__ void read_frag_k32(const char *panel, int r0, int c, int lane,
+                                              u32 (*f)[DT::FDW])
+{
+    const int r = r0 + (lane & 31);
+    const int byte = c * (2 * DT::FDW * 4) + (lane >> 5) * (DT::FDW * 4);
+#pragma unroll
+    for (int h = 0; h < DT::FDW / 4; ++h) {
+        const u32x4 v = *(const u32x4 *)(panel + k_off<KB, true>(r, byte + 16 * h));
+#pragma unroll
+        for (int d = 0; d < 4; ++d) f[0][4 * h + d] = v[d];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // One operand panel of a stage: ROWS rows of m (or n) x KC values of k
 // (KB bytes of k per row), ROWS*KB/1024 blocks of 1 KiB, PER blocks loaded
 // by each of NW waves.
 // ---------------------------------------------------------------------------
-template <class DT, int ROWS, int NW, bool KMODE, int SK = DT::GES, int KB = 128>
+template <class DT, int ROWS, int NW, bool KMODE, int SK = DT::GES, int KB = 128, bool R32 = false>
 struct DPanel {
     static constexpr int GES = DT::GES, KC = KB / GES, VK = 16 / GES;
     static constexpr int NB = ROWS * KB / 1024; // 1 KiB blocks per panel
@@ -185,7 +229,7 @@ struct DPanel {
             const int b = wave * PER + q;
             if constexpr (KMODE) {
                 const int r = (64 / CPK) * b + lane / CPK;
-                const int lc = kslot<KB>(r, lane % CPK);
+                const int lc = kslot<KB, R32>(r, lane % CPK);
                 const int grow = row0 + r, kof = lc * VK;
                 off[q] = ((int64_t)grow * ld + kof) * GES;
                 lim[q] = grow < R ? K - kof : INT_MIN;
@@ -218,7 +262,7 @@ struct DPanel {
         const int lc = valid_k / VK;
         const int keep = (valid_k % VK) * GES;   // bytes of the chunk to keep, 1..15
         for (int r = tid; r < ROWS; r += nt) {
-            u32x4 *p = (u32x4 *)(panel + k_off<KB>(r, lc * 16));
+            u32x4 *p = (u32x4 *)(panel + k_off<KB, R32>(r, lc * 16));
             u32x4 v = *p;
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
@@ -289,6 +333,117 @@ __device__ __forceinline__ void read_frag_tr(const char *panel, int r0, int c, i
     }
 }
 
+// Fragment of the 32-column block at panel offset r0 (m or n) and MFMA chunk
+// c of an m/n-contiguous panel, for the 32x32 MFMAs: lane l holds column
+// r0 + l%32 and the k values of chunk c's lane half l/32, in order.  Each
+// 16-lane group q reads 16 columns (r0 + 16 (q%2) ..) of its k rows with the
+// transposing reads (lane mapping at read_frag_tr): 16-bit, two reads of 4 k
+// rows; 8-bit, FDW/2 reads of 8 k rows.
+template <class DT, int ROWS>
+__device__ __forceinline__ void read_frag_tr32(const char *panel, int r0, int c, int lane,
+                                               u32 (*f)[DT::FDW])
+{
+    constexpr int GES = DT::GES, RB = ROWS * GES, KF32 = DT::KF / 2;
+    const int q = lane >> 4, s = lane & 15;
+    const int col0 = r0 + 16 * (q & 1);
+    if constexpr (GES == 2) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int kr = c * KF32 + 8 * (q >> 1) + 4 * h + (s >> 2);
+            const int byte = (col0 + 4 * (s & 3)) * 2;
+            const i16x4 v =
+                __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)(panel + mn_off<66, RB, 8>(kr, byte)));
+            const u32x2 w = __builtin_bit_cast(u32x2, v);
+            f[0][2 * h] = w[0];
+            f[0][2 * h + 1] = w[1];
+        }
+    } else {
+        static_assert(GES == 1, "transposing 32-column reads of 8- and 16-bit panels");
+#pragma unroll
+        for (int h = 0; h < DT::FDW / 2; ++h) {
+            const int kr = c * KF32 + (KF32 / 2) * (q >> 1) + 8 * h + (s >> 1);
+            const int byte = col0 + 8 * (s & 1);
+            const i32x2 v =
+                __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_i32x2 *)(panel + mn_off<65, RB, 8>(kr, byte)));
+            f[0][2 * h] = (u32)v[0];
+            f[0][2 * h + 1] = (u32)v[1];
+        }
+    }
+}
+
+// 32x32 MFMA accumulators: 16 values per lane; register r of lane l holds
+// row 8 (r/4) + 4 (l/32) + r%4 and column l%32 of the block.
+template <class DT>
+struct Acc32Of {
+    typedef f32x16 type;
+};
+template <>
+struct Acc32Of<TI8> {
+    typedef i32x16 type;
+};
+
+// One 32x32 MFMA step over fragments of KF/2 values of k per lane half
+// (sub-step s of Sub<DT>: FP32 takes one value per lane and step).
+template <class DT>
+__device__ __forceinline__ void mma32(typename Acc32Of<DT>::type &acc, const u32 (*a)[DT::FDW],
+                                      const u32 (*b)[DT::FDW], int s)
+{
+    if constexpr (DT::GES == 4 && !DT::SPLIT) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(float, a[0][s]),
+                                                   __builtin_bit_cast(float, b[0][s]), acc, 0, 0, 0);
+    } else if constexpr (DT::GES == 2) {
+        u32x4 xv = {a[0][0], a[0][1], a[0][2], a[0][3]}, yv = {b[0][0], b[0][1], b[0][2], b[0][3]};
+        if constexpr (DT::HALF)
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, xv),
+                                                         __builtin_bit_cast(f16x8, yv), acc, 0, 0, 0);
+        else
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, xv),
+                                                          __builtin_bit_cast(bf16x8, yv), acc, 0, 0, 0);
+    } else if constexpr (DT::INT) {
+        i32x4 xv = {(int)a[0][0], (int)a[0][1], (int)a[0][2], (int)a[0][3]};
+        i32x4 yv = {(int)b[0][0], (int)b[0][1], (int)b[0][2], (int)b[0][3]};
+        acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(xv, yv, acc, 0, 0, 0);
+    } else {
+        static_assert(DT::GES == 1 && DT::FDW == 8, "FP8: 32 bytes of k per lane");
+        i32x8 xv, yv;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            xv[d] = (int)a[0][d];
+            yv[d] = (int)b[0][d];
+        }
+        acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(xv, yv, acc, 0, 0, 0, 127, 0, 127);
+    }
+}
+
+template <class DT, int FM, int FN>
+__device__ __forceinline__ void store_c32(const GemmArgs &p, const typename Acc32Of<DT>::type (*acc)[FN],
+                                          int r0, int c0, int lane)
+{
+    const int col_l = lane & 31, row_l = 4 * (lane >> 5);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = r0 + 32 * i + 8 * (r >> 2) + row_l + (r & 3);
+                const int col = c0 + 32 * j + col_l;
+                if (row < p.m && col < p.n) {
+                    if constexpr (DT::INT) {
+                        int *c = (int *)p.C + (int64_t)row * p.ldc + col;
+                        u32 v = (u32)p.ialpha * (u32)acc[i][j][r];
+                        if (p.ibeta != 0) v += (u32)p.ibeta * (u32)(*c);
+                        *c = (int)v;
+                    } else {
+                        float *c = (float *)p.C + (int64_t)row * p.ldc + col;
+                        float v = p.alpha * acc[i][j][r];
+                        if (p.beta != 0.0f) v = __builtin_fmaf(p.beta, *c, v);
+                        *c = v;
+                    }
+                }
+            }
+}
+
 // ---------------------------------------------------------------------------
 // The direct-staged tile: C[m0:m0+MC, n0:n0+NC] = alpha op(A) op(B) + beta C
 // with an NS-deep ring of LDS stages.  Requires 16-byte aligned operands and
@@ -300,27 +455,35 @@ __device__ __forceinline__ void read_frag_tr(const char *panel, int r0, int c, i
 // each barrier with no MFMA to issue).  The deferred fragments are already in
 // registers; each wave waits for its LDS reads to land before the barrier,
 // so no load of the next stage can overwrite LDS that is still being read.
+// MB: the MFMA block, 16 (16x16 MFMAs) or 32 (32x32 MFMAs: twice the
+// multiply-adds per fragment byte read from LDS, 16 accumulators per lane
+// and block; 128-byte stages, 8- and 16-bit types).
 template <class DT, int MC, int NC, int WM, int WN, bool TA, bool TB, int NS, int KB = 128,
-          bool OVL = false>
+          bool OVL = false, int MB = 16>
 struct DTile {
     static constexpr int NW = WM * WN, NT = 64 * NW;
     static constexpr int KC = KB / DT::GES;
     static constexpr int WTM = MC / WM, WTN = NC / WN;
-    static constexpr int FM = WTM / 16, FN = WTN / 16;
+    static constexpr int FM = WTM / MB, FN = WTN / MB;
     static constexpr int PANEL_A = MC * KB, PANEL_B = NC * KB;
     static constexpr int STAGE_BYTES = PANEL_A + PANEL_B;
     static constexpr int LDS_BYTES = NS * STAGE_BYTES;
     static constexpr int MINB = 1;
-    static constexpr int NCH = KC / DT::KF;   // fragment chunks per stage
-    typedef DPanel<DT, MC, NW, !TA, DT::GES, KB> PA;   // A 'N' is contiguous along k
-    typedef DPanel<DT, NC, NW, TB, DT::GES, KB> PB;    // B 'T' is contiguous along k
-    static_assert(KC % DT::KF == 0, "a stage holds whole fragments");
+    static constexpr int KF = MB == 16 ? DT::KF : DT::KF / 2;   // k of one fragment chunk
+    static constexpr int NCH = KC / KF;                         // fragment chunks per stage
+    static constexpr bool W32 = MB == 32;
+    static constexpr int SKX = W32 ? 64 + DT::GES : DT::GES;    // m/n panel read pattern
+    typedef DPanel<DT, MC, NW, !TA, SKX, KB, W32> PA;   // A 'N' is contiguous along k
+    typedef DPanel<DT, NC, NW, TB, SKX, KB, W32> PB;    // B 'T' is contiguous along k
+    static_assert(KC % KF == 0, "a stage holds whole fragments");
+    static_assert(MB == 16 || (MB == 32 && KB == 128 && (DT::GES == 1 || DT::GES == 2)),
+                  "32x32 MFMA tiles: 8- and 16-bit types, 128-byte stages");
     static constexpr int LOADS = PA::PER + PB::PER;
     static_assert(DT::LES == DT::GES && DT::PLANES == 1, "direct staging keeps the input format");
     static_assert(NS >= 2 && LDS_BYTES <= 160 * 1024, "LDS budget of one CU");
     static_assert((NS - 2) * LOADS < 64, "loads in flight must fit the vmcnt counter");
-    static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile must be whole MFMA blocks");
-    typedef typename AccOf<DT>::type Acc;
+    static_assert(WTM % MB == 0 && WTN % MB == 0, "wave tile must be whole MFMA blocks");
+    typedef typename std::conditional<W32, typename Acc32Of<DT>::type, typename AccOf<DT>::type>::type Acc;
 
     static __device__ __forceinline__ void read_chunk(const char *buf, int c, int wm, int wn,
                                                       int lane, u32 (*fa)[1][DT::FDW],
@@ -329,14 +492,31 @@ struct DTile {
         const char *pa = buf, *pb = buf + PANEL_A;
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
-            if constexpr (!TA) read_frag_k<DT, KB>(pa, wm * WTM + 16 * i, c, lane, fa[i]);
-            else read_frag_tr<DT, MC>(pa, wm * WTM + 16 * i, c, lane, fa[i]);
+            if constexpr (W32) {
+                if constexpr (!TA) read_frag_k32<DT, KB>(pa, wm * WTM + MB * i, c, lane, fa[i]);
+                else read_frag_tr32<DT, MC>(pa, wm * WTM + MB * i, c, lane, fa[i]);
+            } else {
+                if constexpr (!TA) read_frag_k<DT, KB>(pa, wm * WTM + 16 * i, c, lane, fa[i]);
+                else read_frag_tr<DT, MC>(pa, wm * WTM + 16 * i, c, lane, fa[i]);
+            }
         }
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-            if constexpr (TB) read_frag_k<DT, KB>(pb, wn * WTN + 16 * j, c, lane, fb[j]);
-            else read_frag_tr<DT, NC>(pb, wn * WTN + 16 * j, c, lane, fb[j]);
+            if constexpr (W32) {
+                if constexpr (TB) read_frag_k32<DT, KB>(pb, wn * WTN + MB * j, c, lane, fb[j]);
+                else read_frag_tr32<DT, NC>(pb, wn * WTN + MB * j, c, lane, fb[j]);
+            } else {
+                if constexpr (TB) read_frag_k<DT, KB>(pb, wn * WTN + 16 * j, c, lane, fb[j]);
+                else read_frag_tr<DT, NC>(pb, wn * WTN + 16 * j, c, lane, fb[j]);
+            }
         }
+    }
+
+    static __device__ __forceinline__ void mma(Acc &acc, const u32 (*fa)[DT::FDW],
+                                               const u32 (*fb)[DT::FDW], int st)
+    {
+        if constexpr (W32) mma32<DT>(acc, fa, fb, st);
+        else mma_step<DT>(acc, fa, fb, st);
     }
 
     static __device__ __forceinline__ void mfma_chunk(Acc (*acc)[FN], const u32 (*fa)[1][DT::FDW],
@@ -347,7 +527,7 @@ struct DTile {
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
-                for (int j = 0; j < FN; ++j) mma_step<DT>(acc[i][j], fa[i], fb[j], st);
+                for (int j = 0; j < FN; ++j) mma(acc[i][j], fa[i], fb[j], st);
     }
 
     // The micro-kernel over one stage; the fragments of chunk c+1 are read
@@ -366,7 +546,7 @@ struct DTile {
                 for (int i = 0; i < FM; ++i)
 #pragma unroll
                     for (int j = 0; j < FN; ++j)
-                        mma_step<DT>(acc[i][j], fa[c & 1][i], fb[c & 1][j], st);
+                        mma(acc[i][j], fa[c & 1][i], fb[c & 1][j], st);
         }
     }
 
@@ -381,7 +561,7 @@ struct DTile {
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < FN; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+            for (int j = 0; j < FN; ++j) acc[i][j] = Acc{};
 
         const bool form = p.k > 0 && alpha_nonzero<DT>(p);
         const int nk = form ? (p.k + KC - 1) / KC : 0;
@@ -462,7 +642,8 @@ struct DTile {
             wait_vm<0>();
             __builtin_amdgcn_s_barrier();
         }
-        store_c<DT, FM, FN>(p, acc, m0 + wm * WTM, n0 + wn * WTN, lane);
+        if constexpr (W32) store_c32<DT, FM, FN>(p, acc, m0 + wm * WTM, n0 + wn * WTN, lane);
+        else store_c<DT, FM, FN>(p, acc, m0 + wm * WTM, n0 + wn * WTN, lane);
     }
 };
 

@@ -96,19 +96,19 @@ static void add_resident_family(std::vector<KernelCfg> &out, int kclass)
 // vectorised variant of all four transpositions; unaligned operands fall
 // back to the class's configuration 0.
 template <class DT, int MC, int NC, int WM, int WN, int NS, bool TA, bool TB, bool SPLITK, int KB,
-          bool OVL = false>
+          bool OVL = false, int MB = 16>
 static void fill_direct(KernelCfg &c)
 {
-    typedef DTile<DT, MC, NC, WM, WN, TA, TB, NS, KB, OVL> T;
+    typedef DTile<DT, MC, NC, WM, WN, TA, TB, NS, KB, OVL, MB> T;
     c.func[2 * TA + TB][1] = (const void *)&gemm_direct_kernel<T>;
     if constexpr (SPLITK) c.splitk[2 * TA + TB][1] = (const void *)&gemm_splitk_kernel<T, DT::GES, TA, TB>;
 }
 
 template <class DT, int MC, int NC, int WM, int WN, int NS, bool SPLITK = false, int KB = 128,
-          bool OVL = false>
+          bool OVL = false, int MB = 16>
 static void add_direct(std::vector<KernelCfg> &out, int kclass)
 {
-    typedef DTile<DT, MC, NC, WM, WN, false, false, NS, KB, OVL> T;
+    typedef DTile<DT, MC, NC, WM, WN, false, false, NS, KB, OVL, MB> T;
     KernelCfg c;
     c.kclass = kclass;
     c.mc = MC;
@@ -121,10 +121,11 @@ static void add_direct(std::vector<KernelCfg> &out, int kclass)
     c.stages = NS;
     c.kind = 0;
     c.direct = true;
-    fill_direct<DT, MC, NC, WM, WN, NS, false, false, SPLITK, KB, OVL>(c);
-    fill_direct<DT, MC, NC, WM, WN, NS, false, true, SPLITK, KB, OVL>(c);
-    fill_direct<DT, MC, NC, WM, WN, NS, true, false, SPLITK, KB, OVL>(c);
-    fill_direct<DT, MC, NC, WM, WN, NS, true, true, SPLITK, KB, OVL>(c);
+    c.mfma = MB;
+    fill_direct<DT, MC, NC, WM, WN, NS, false, false, SPLITK, KB, OVL, MB>(c);
+    fill_direct<DT, MC, NC, WM, WN, NS, false, true, SPLITK, KB, OVL, MB>(c);
+    fill_direct<DT, MC, NC, WM, WN, NS, true, false, SPLITK, KB, OVL, MB>(c);
+    fill_direct<DT, MC, NC, WM, WN, NS, true, true, SPLITK, KB, OVL, MB>(c);
     out.push_back(c);
 }
 

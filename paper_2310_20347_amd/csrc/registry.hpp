@@ -30,6 +30,7 @@ struct KernelCfg {
     int kind = 0;           // 0: C resident; 1..4: operand resident; 5: packed split; 6: split-K;
                             // 7: digit products (INT16 / INT32 on the INT8 tiles)
     bool direct = false;    // stages fed by direct global -> LDS loads
+    int mfma = 16;          // MFMA block of the wave tile: 16 (16x16 MFMAs) or 32 (32x32)
     int packed = -1;        // packed split: registry index of the bf16 tile run on the packed operands
     int base = -1;          // split-K: registry index of the tile it slices
     int unpacked = 0;       // packing configuration: bit 0 A, bit 1 B loaded straight to registers
@@ -58,6 +59,7 @@ void register_direct_half_late(std::vector<KernelCfg> &out);
 void register_direct_byte_late(std::vector<KernelCfg> &out);
 void register_f64_late(std::vector<KernelCfg> &out);
 void register_int_late(std::vector<KernelCfg> &out);
+void register_direct_w32_late(std::vector<KernelCfg> &out);
 void register_direct_half(std::vector<KernelCfg> &out);
 void register_direct_byte(std::vector<KernelCfg> &out);
 void register_nopack(std::vector<KernelCfg> &out);

@@ -1,9 +1,10 @@
 """The FP8 MFMA's accumulation precision, measured through the library: every
 product of two E4M3 values is exact in FP32, yet one instruction sums its
-128 products with about 12 bits relative to the largest of them.  With
-k = 128 (one instruction per output) the error of each C entry against the
-exact sum of its decoded products, divided by that entry's largest |product|,
-stays within 2^-11 (the allowance the FP8 parity tolerance adds per 128-long
+products (128 for the 16x16 form, 64 for the 32x32 one) with about 12 bits
+relative to the largest of them.  With k equal to one instruction's k (one
+instruction per output) the error of each C entry against the exact sum of
+its decoded products, divided by that entry's largest |product|, stays
+within 2^-11 (the allowance the FP8 parity tolerance adds per instruction's
 chunk of k) and is far above FP32 accumulation's rounding (the sums are not
 exact).  Small-integer data, whose products and sums are exact in fewer
 bits, come out exact."""
@@ -18,7 +19,16 @@ from paper_2310_20347_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-def _run(a32, b32):
+def _config(form):
+    """The first configuration whose wave tiles are made of form x form MFMAs."""
+    ids = [i for i in range(mg.num_configs(mg.GEMM_F8E4M3))
+           if mg.config_info(mg.GEMM_F8E4M3, i)["mfma"] == form
+           and mg.config_supports(mg.GEMM_F8E4M3, i, "N", "N")]
+    assert ids, f"no {form}x{form} FP8 configuration"
+    return ids[0]
+
+
+def _run(a32, b32, cfg):
     import torch
     gpu_init()
     m, k = a32.shape
@@ -26,19 +36,25 @@ def _run(a32, b32):
     A = inputs.to_e4m3_bits(a32)
     B = inputs.to_e4m3_bits(b32)
     C = torch.empty((m, n), dtype=torch.float32, device="cuda")
-    mg.gemm("N", "N", m, n, k, 1.0, torch.from_numpy(A).cuda(), k, torch.from_numpy(B).cuda(), n,
-            0.0, C, n, mg.GEMM_F8E4M3)
-    torch.cuda.synchronize()
+    mg.force_config(mg.GEMM_F8E4M3, cfg, 0)
+    try:
+        mg.gemm("N", "N", m, n, k, 1.0, torch.from_numpy(A).cuda(), k, torch.from_numpy(B).cuda(),
+                n, 0.0, C, n, mg.GEMM_F8E4M3)
+        torch.cuda.synchronize()
+        assert mg.last_config()["cfg"] == cfg
+    finally:
+        mg.force_config(mg.GEMM_F8E4M3, -1, 0)
     return C.cpu().numpy().astype(np.float64), oracle.decode_e4m3(A).reshape(m, k), \
         oracle.decode_e4m3(B).reshape(k, n)
 
 
-def test_fp8_mfma_sums_with_about_12_bits():
+@pytest.mark.parametrize("form", [16, 32], ids=["16x16x128", "32x32x64"])
+def test_fp8_mfma_sums_with_about_12_bits(form):
     m = n = 128
-    k = 128
+    k = 128 if form == 16 else 64
     a32 = inputs.normal((m, k), 501)
     b32 = inputs.normal((k, n), 502)
-    C, Ad, Bd = _run(a32, b32)
+    C, Ad, Bd = _run(a32, b32, _config(form))
     exact = Ad @ Bd                                        # products exact, summed in FP64
     pmax = np.abs(Ad)[:, :, None] * np.abs(Bd)[None, :, :]
     pmax = pmax.max(axis=1)                                # largest |a_ip b_pj| per entry
@@ -51,9 +67,10 @@ def test_fp8_mfma_sums_with_about_12_bits():
     assert worst >= 2.0 ** -16
 
 
-def test_fp8_small_integers_exact():
+@pytest.mark.parametrize("form", [16, 32], ids=["16x16x128", "32x32x64"])
+def test_fp8_small_integers_exact(form):
     k = 128
     a32 = inputs.small_ints((64, k), 503, -4, 4)
     b32 = inputs.small_ints((k, 64), 504, -4, 4)
-    C, Ad, Bd = _run(a32, b32)
+    C, Ad, Bd = _run(a32, b32, _config(form))
     assert np.array_equal(C, Ad @ Bd)
