@@ -39,6 +39,9 @@ def parse():
                    help="only the timed steps (for rocprofv3 runs)")
     p.add_argument("--profile-precision", action="store_true",
                    help="only the 8192^3 GEMM of every precision path (for rocprofv3 runs)")
+    p.add_argument("--profile-tiles", action="store_true",
+                   help="only 8192^3 BF16/FP16/FP8/INT8 GEMMs, once per 8-wave 256x256 tile "
+                        "variant (MFMA form, stage size, ring depth; for rocprofv3 runs)")
     p.add_argument("--profile-grouped", action="store_true",
                    help="only the 512-GEMM grouped launches, split x3 and INT8 (for rocprofv3 runs)")
     p.add_argument("--calib-copy", action="store_true",
@@ -136,6 +139,9 @@ def main():
     stream = torch.cuda.current_stream()
     if args.profile_precision:
         print(json.dumps({"precision_8192": precision_8192(mg, torch, stream)}), flush=True)
+        return
+    if args.profile_tiles:
+        print(json.dumps({"tiles_8192": tile_variants_8192(mg, torch, stream)}), flush=True)
         return
     if args.profile_grouped:
         if args.calib_copy:
@@ -401,6 +407,51 @@ def precision_8192(mg, torch, stream):
     del ai, bi
     prec.update(integer_paths(mg, torch, stream, Ci))
     return prec
+
+
+def tile_variants_8192(mg, torch, stream):
+    """8192^3 'N','N' in BF16, FP16, FP8 and INT8 with each 8-wave 256x256
+    direct-staged tile: 16x16 or 32x32 MFMA blocks, 128- or 64-byte stages,
+    ring depth; the kernel names in a trace tell the deferred-chunk schedule
+    apart."""
+    from paper_2310_20347_amd import inputs
+    n = 8192
+    a32 = inputs.normal((n, n), inputs.seed_for(3, "A"))
+    b32 = inputs.normal((n, n), inputs.seed_for(3, "B"))
+    out = {}
+    for name, dt, enc, es, peak in (("bf16", mg.GEMM_BF16, inputs.to_bf16_bits, 2, 2516.6),
+                                    ("f16", mg.GEMM_F16, inputs.to_f16_bits, 2, 2516.6),
+                                    ("e4m3", mg.GEMM_F8E4M3, inputs.to_e4m3_bits, 1, 5033.0),
+                                    ("i8", mg.GEMM_I8, None, 1, 5033.0)):
+        if enc is None:
+            Ad = torch.from_numpy(inputs.int8_uniform((n, n), 41)).cuda()
+            Bd = torch.from_numpy(inputs.int8_uniform((n, n), 42)).cuda()
+            Cd = torch.empty((n, n), dtype=torch.int32, device="cuda")
+        else:
+            ea, eb = enc(a32), enc(b32)
+            if es == 2:
+                ea, eb = ea.view(np.int16), eb.view(np.int16)
+            Ad, Bd = torch.from_numpy(ea).cuda(), torch.from_numpy(eb).cuda()
+            Cd = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        rows = {}
+        for cfg in range(mg.num_configs(dt)):
+            info = mg.config_info(dt, cfg)
+            if not (info["staging"] == "direct" and info["kind"] == 0 and info["mc"] == 256
+                    and info["nc"] == 256 and info["threads"] == 512):
+                continue
+            stage = info["kc"] * es
+            depth = info["lds_bytes"] // (512 * stage)
+            mg.force_config(dt, cfg, 1)
+            ms = _time_call(lambda: mg.gemm("N", "N", n, n, n, 1, Ad, n, Bd, n, 0, Cd, n, dt,
+                                            stream=stream), torch, stream, reps=3)
+            tf = 2.0 * n ** 3 / ms / 1e9
+            rows[f"cfg{cfg}"] = {"mfma": info["mfma"], "stage_bytes": stage, "stages": depth,
+                                 "ms": round(ms, 3), "tflops": round(tf, 1),
+                                 "mfma_util": round(tf / peak, 4)}
+        mg.force_config(dt, -1, 0)
+        out[name] = rows
+        del Ad, Bd, Cd
+    return out
 
 
 def integer_paths(mg, torch, stream, C):

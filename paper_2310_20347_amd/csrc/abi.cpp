@@ -191,6 +191,7 @@ void ensure_registered()
     register_int_late(g_cfgs);
     const size_t nw32 = g_cfgs.size();
     register_direct_w32_late(g_cfgs);
+    register_direct_deep_late(g_cfgs);
     add_packed(nw32, g_cfgs.size());
     for (size_t i = 0; i < g_cfgs.size(); ++i) g_by_class[g_cfgs[i].kclass].push_back((int)i);
     g_registered = true;

@@ -76,6 +76,9 @@ __device__ __forceinline__ void wait_vm()
 // of the LDS cycles of those reads were bank conflicts).
 //   SK 4: FP32 MFMA fragment, 32-bit reads; group g reads 64 bytes of row 4g+d.
 //   SK 8: FP32 read of the split product; group g reads 64 bytes of row 8g+e.
+//   SK 9: FP64 MFMA fragment, 64-bit reads; group g reads 128 bytes of row
+//         2g+e, so the pair served together reads rows kr and kr+2 (rows of
+//         512 bytes or more: row bit 1 picks the half line).
 //   SK 2: 16-bit transposing read; group g reads 4 rows (8g + 4h + 0..3) of
 //         32 bytes, groups GS = 8 rows apart.
 //   SK 1: 8-bit transposing read; group g reads 8 rows (GS*g + 8h + 0..7) of
@@ -109,6 +112,10 @@ __device__ __forceinline__ int mn_chunk(int kr, int lc)
         } else {
             x = 2 * ((kr >> 1) & 3);
         }
+    } else if constexpr (SK == 9) {
+        static_assert(RB >= 256, "FP64 panels have rows of 256 bytes or more");
+        x = 8 * ((kr >> 1) & 1);
+        mask = 15;
     } else if constexpr (SK == 8) {
         x = 4 * ((kr >> 3) & 1);
     } else if constexpr (SK == 4) {
@@ -303,7 +310,7 @@ __device__ __forceinline__ void read_frag_tr(const char *panel, int r0, int c, i
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int kr = c * DT::KF + 2 * g + e;
-            const u32x2 v = *(const u32x2 *)(panel + mn_off<8, RB, 8>(kr, (r0 + s) * 8));
+            const u32x2 v = *(const u32x2 *)(panel + mn_off<9, RB, 8>(kr, (r0 + s) * 8));
             f[0][2 * e] = v[0];
             f[0][2 * e + 1] = v[1];
         }
@@ -472,7 +479,8 @@ struct DTile {
     static constexpr int KF = MB == 16 ? DT::KF : DT::KF / 2;   // k of one fragment chunk
     static constexpr int NCH = KC / KF;                         // fragment chunks per stage
     static constexpr bool W32 = MB == 32;
-    static constexpr int SKX = W32 ? 64 + DT::GES : DT::GES;    // m/n panel read pattern
+    // m/n panel read pattern (the swizzle of mn_chunk)
+    static constexpr int SKX = W32 ? 64 + DT::GES : (DT::GES == 8 ? 9 : DT::GES);
     typedef DPanel<DT, MC, NW, !TA, SKX, KB, W32> PA;   // A 'N' is contiguous along k
     typedef DPanel<DT, NC, NW, TB, SKX, KB, W32> PB;    // B 'T' is contiguous along k
     static_assert(KC % KF == 0, "a stage holds whole fragments");
@@ -583,12 +591,17 @@ struct DTile {
             const bool ragged = (!TA || TB) && (p.k % PA::VK) != 0;
             int rd = 0, wr = NS - 1;   // ring buffers: stage being read, stage being loaded
             if constexpr (OVL) {
-                // (with one chunk per stage both buffers would hold a whole
-                // stage's fragments, which spills the 256x256 tiles)
-                static_assert(NCH % 2 == 0, "the deferred chunk and the next stage's first chunk "
-                                            "use different fragment buffers");
+                // Fragment buffers alternate by chunk: with an even number of
+                // chunks per stage every stage starts in buffer 0 and its
+                // last chunk is in buffer 1; with one chunk per stage the
+                // deferred chunk is the whole previous stage, and stages
+                // alternate buffers (the loop runs stages in pairs, so every
+                // buffer index is a compile-time constant).
+                static_assert(NCH % 2 == 0 || NCH == 1, "the deferred chunk and the next stage's "
+                                                        "first chunk use different fragment buffers");
                 u32 fa[2][FM][1][DT::FDW], fb[2][FN][1][DT::FDW];
-                for (int s = 0; s < nk; ++s) {
+                auto stage = [&](int s, auto parity) __attribute__((always_inline)) {
+                    constexpr int P = decltype(parity)::value;
                     // this wave's loads of stage s have landed and its reads of
                     // stage s-1 (the deferred fragments) are in registers ...
                     __builtin_amdgcn_s_waitcnt(((NS - 2) * LOADS & 15) | (((NS - 2) * LOADS >> 4) << 14) |
@@ -606,8 +619,8 @@ struct DTile {
                     pa.issue(A, p.lda, (s + NS - 1) * KC, nxt, wave);
                     pb.issue(B, p.ldb, (s + NS - 1) * KC, nxt + PANEL_A, wave);
                     pin_order();
-                    read_chunk(cur, 0, wm, wn, lane, fa[0], fb[0]);
-                    if (s > 0) mfma_chunk(acc, fa[1], fb[1]);   // stage s-1's last chunk
+                    read_chunk(cur, 0, wm, wn, lane, fa[P], fb[P]);
+                    if (s > 0) mfma_chunk(acc, fa[1 - P], fb[1 - P]);   // stage s-1's last chunk
 #pragma unroll
                     for (int c = 0; c + 1 < NCH; ++c) {
                         read_chunk(cur, c + 1, wm, wn, lane, fa[(c + 1) & 1], fb[(c + 1) & 1]);
@@ -615,8 +628,21 @@ struct DTile {
                     }
                     rd = rd + 1 == NS ? 0 : rd + 1;
                     wr = wr + 1 == NS ? 0 : wr + 1;
+                };
+                if constexpr (NCH == 1) {
+                    // the first stage's parity is chosen so that the last
+                    // stage is read into buffer 1
+                    int s = 0;
+                    if (nk & 1) stage(s++, std::integral_constant<int, 1>());
+                    for (; s < nk; s += 2) {
+                        stage(s, std::integral_constant<int, 0>());
+                        stage(s + 1, std::integral_constant<int, 1>());
+                    }
+                    mfma_chunk(acc, fa[1], fb[1]);   // the last stage
+                } else {
+                    for (int s = 0; s < nk; ++s) stage(s, std::integral_constant<int, 0>());
+                    mfma_chunk(acc, fa[1], fb[1]);   // the last stage's last chunk
                 }
-                mfma_chunk(acc, fa[1], fb[1]);   // the last stage's last chunk
             } else
             for (int s = 0; s < nk; ++s) {
                 wait_vm<(NS - 2) * LOADS>();   // this wave's loads of stage s have landed

@@ -60,6 +60,7 @@ void register_direct_byte_late(std::vector<KernelCfg> &out);
 void register_f64_late(std::vector<KernelCfg> &out);
 void register_int_late(std::vector<KernelCfg> &out);
 void register_direct_w32_late(std::vector<KernelCfg> &out);
+void register_direct_deep_late(std::vector<KernelCfg> &out);
 void register_direct_half(std::vector<KernelCfg> &out);
 void register_direct_byte(std::vector<KernelCfg> &out);
 void register_nopack(std::vector<KernelCfg> &out);
