@@ -6,9 +6,10 @@
 // raster order and runs the tile body (the same C-resident tile as the
 // single-GEMM kernel).  Tile ids beyond each workgroup's first come from
 // atomic counters (one per XCD group), each claimed at the start of the tile
-// before it; the last workgroup to finish resets the counters to zero, so a
-// launch leaves them ready for the next one (no memset node is needed, which
-// keeps the launch capturable in a graph).
+// before it; a workgroup whose group has run out of tiles takes them from the
+// other groups' counters.  The last workgroup to finish resets the counters
+// to zero, so a launch leaves them ready for the next one (no memset node is
+// needed, which keeps the launch capturable in a graph).
 #pragma once
 
 #include "direct.hpp"
@@ -186,21 +187,40 @@ __global__ void __launch_bounds__(256, BODIES::MINB) grouped_kernel(const char *
     const int lane = threadIdx.x & 63;
     const int L = min((int)gridDim.x, kGroups);
     const int g = blockIdx.x % L;
-    const int members = ((int)gridDim.x - g + L - 1) / L;   // workgroups of group g
-    // position v of group g -> global tile id
-    auto tile_of = [&](int v) { return ((v / kChunk) * L + g) * kChunk + v % kChunk; };
+    // position v of group h -> global tile id; positions 0 .. members(h)-1
+    // are the first tiles of group h's workgroups, later ones are claimed
+    auto tile_in = [&](int h, int v) { return ((v / kChunk) * L + h) * kChunk + v % kChunk; };
+    auto members = [&](int h) { return ((int)gridDim.x - h + L - 1) / L; };
+    // Work stealing (thread 0's state): a workgroup draws from its own
+    // group's queue, and once that has drained, from the following groups'
+    // in turn; a drained queue costs one more claim, so every workgroup ends
+    // after at most L - 1 of them.
+    int src = g, drained = 0;
+    auto advance = [&](int nt) {
+        while (nt >= total && ++drained < L) {
+            src = src + 1 == L ? 0 : src + 1;
+            nt = tile_in(src, members(src) + atomicAdd(&counters[src], 1));
+        }
+        return nt;
+    };
     const bool in_lds = count <= kLdsPrefix;
     if (in_lds) {
         for (int i = threadIdx.x; i < count; i += blockDim.x) s_ts[i] = ts[i];
         __syncthreads();
     }
     const int *pre = in_lds ? (const int *)s_ts : ts;
-    int t = tile_of((int)blockIdx.x / L);
+    int t = tile_in(g, (int)blockIdx.x / L);
+    if (t >= total) {   // fewer tiles in this group than workgroups: steal at once
+        if (threadIdx.x == 0) s_next = advance(t);
+        __syncthreads();
+        t = __builtin_amdgcn_readfirstlane(s_next);
+        __syncthreads();
+    }
     while (t < total) {
         // claim the next tile now and use the claim after this tile: the
         // atomic's round trip overlaps the tile instead of delaying its start
         int claim = 0;
-        if (threadIdx.x == 0) claim = atomicAdd(&counters[g], 1);
+        if (threadIdx.x == 0) claim = atomicAdd(&counters[src], 1);
         // last problem whose first tile is <= t: 64-way search per wave over
         // the compact prefix array (in LDS, or two dependent loads for up to
         // 4096 problems)
@@ -220,7 +240,7 @@ __global__ void __launch_bounds__(256, BODIES::MINB) grouped_kernel(const char *
         int tm, tn;
         raster(t - pre[lo], p.tiles_m, p.tiles_n, p.order, p.group, tm, tn);
         BODIES::run(body, p, tm, tn, lds);
-        if (threadIdx.x == 0) s_next = tile_of(members + claim);
+        if (threadIdx.x == 0) s_next = advance(tile_in(src, members(src) + claim));
         __syncthreads();
         t = __builtin_amdgcn_readfirstlane(s_next);
         __syncthreads();
