@@ -527,6 +527,29 @@ struct DTile {
         else mma_step<DT>(acc, fa, fb, st);
     }
 
+    // Scheduling hint for a chunk's fragment reads issued with the previous
+    // chunk's MFMAs: alternate one LDS read with an even share of the MFMAs,
+    // so the reads spread over the MFMA chain instead of bunching at its start
+    // (the instruction order only; every accumulator sees the same MFMAs in
+    // the same order).  Given to tiles of one wave per SIMD, which have no
+    // second wave to issue MFMAs while one waits for its reads; in the 8-wave
+    // tiles it gained 1-2% and made some layouts spill.
+    static __device__ __forceinline__ void interleave_reads()
+    {
+        if constexpr (NW != 4) return;
+        constexpr int RK = DT::FDW / 4 > 0 ? DT::FDW / 4 : 1;   // 128-bit reads per k-contiguous fragment
+        constexpr int RT = W32 || DT::GES <= 2 ? (DT::GES == 2 ? 2 : DT::FDW / 2)
+                                               : (DT::GES == 8 ? 2 : 4);   // reads per m/n fragment
+        constexpr int R = FM * (TA ? RT : RK) + FN * (TB ? RK : RT);
+        constexpr int M = FM * FN * Sub<DT>::value;
+        constexpr int PER = M / R > 0 ? M / R : 1;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);     // one LDS read
+            __builtin_amdgcn_sched_group_barrier(0x008, PER, 0);   // then PER MFMAs
+        }
+    }
+
     static __device__ __forceinline__ void mfma_chunk(Acc (*acc)[FN], const u32 (*fa)[1][DT::FDW],
                                                       const u32 (*fb)[1][DT::FDW])
     {
@@ -625,6 +648,7 @@ struct DTile {
                     for (int c = 0; c + 1 < NCH; ++c) {
                         read_chunk(cur, c + 1, wm, wn, lane, fa[(c + 1) & 1], fb[(c + 1) & 1]);
                         mfma_chunk(acc, fa[c & 1], fb[c & 1]);
+                        interleave_reads();
                     }
                     rd = rd + 1 == NS ? 0 : rd + 1;
                     wr = wr + 1 == NS ? 0 : wr + 1;
