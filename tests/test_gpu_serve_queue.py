@@ -2,6 +2,7 @@
 ring): every sampled request's result equals the same GEMM run alone through
 gemm() bit for bit and matches the oracle; the kernel's bounded idle exit
 and the host's relaunch lose no work."""
+import numpy as np
 import pytest
 
 import paper_2310_20347_amd as mg
@@ -16,6 +17,28 @@ def test_queue_results_same_alone_and_in_the_mix():
     mg.gemm_init(None)
     pools = Pools(64 << 20, seed=9101)
     reqs, meta = workload(600, 5000.0, 9102, pools, lo=16, hi=1024, result_every=15)
+    # a burst: 60 requests arrive together, among them three with a dimension
+    # of 4096 (the batching workload's upper end), so their tiles share the
+    # ring and the workgroups
+    t0 = reqs[100].arrival_s
+    for i in range(100, 160):
+        reqs[i].arrival_s = t0
+    for j, (m, n, k) in enumerate([(4096, 256, 512), (384, 4096, 256), (256, 640, 4096)]):
+        r, md = workload(1, 1.0, 9150 + j, pools, lo=16, hi=16, result_every=1)
+        md = md[0]
+        dt = md["dtype"]
+        lda, ldb, ldc, _ = sv.serve_layout(m, n, k, dt)
+        md.update(m=m, n=n, k=k, lda=lda, ldb=ldb, ldc=ldc, a_off=0, b_off=0,
+                  result=np.zeros((m, n), dtype=np.int32 if dt == mg.GEMM_I8 else np.float32))
+        reqs[110 + j] = sv.Request(t0, m, n, k, dt, pools.ptr(dt, 0), pools.ptr(dt, 0),
+                                   md["result"].ctypes.data)
+        meta[110 + j] = md
+    for i in range(100, 160, 3):   # results of several burst members
+        md = meta[i]
+        if md["result"] is None:
+            md["result"] = np.zeros((md["m"], md["n"]),
+                                    dtype=np.int32 if md["dtype"] == mg.GEMM_I8 else np.float32)
+            reqs[i].result = md["result"].ctypes.data
     cfg = sv.config(budget_bytes=2 << 30, max_active=256, warmup_requests=50, watchdog_s=20.0)
     print("queue mode: 600 requests at 5k req/s", flush=True)
     rc, st, oc = sv.serve_run_queue(cfg, reqs)
@@ -26,7 +49,13 @@ def test_queue_results_same_alone_and_in_the_mix():
     assert st.peak_arena_bytes <= cfg.budget_bytes
     assert st.p50_ms > 0 and st.p99_ms >= st.p50_ms
     assert all(o.status == 0 for o in oc)
-    assert check_results(pools, meta) >= 30
+    # every checked burst member was in flight together with another request
+    for i in range(100, 160):
+        if meta[i]["result"] is None:
+            continue
+        assert any(j != i and oc[j].admit_s < oc[i].done_s and oc[i].admit_s < oc[j].done_s
+                   for j in range(100, 160)), f"request {i} ran alone"
+    assert check_results(pools, meta) >= 50
 
 
 def test_queue_idle_exit_and_relaunch_lose_no_work():
