@@ -426,29 +426,42 @@ template <class DT, int FM, int FN>
 __device__ __forceinline__ void store_c32(const GemmArgs &p, const typename Acc32Of<DT>::type (*acc)[FN],
                                           int r0, int c0, int lane)
 {
+    typedef typename std::conditional<DT::INT, int, float>::type CT;
     const int col_l = lane & 31, row_l = 4 * (lane >> 5);
+    const bool read_c = DT::INT ? p.ibeta != 0 : p.beta != 0.0f;
+    CT *const C = (CT *)p.C;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
+        for (int j = 0; j < FN; ++j) {
+            // the block's C values are all read before any is written (as in store_c)
+            CT cv[16];
+            if (read_c) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = r0 + 32 * i + 8 * (r >> 2) + row_l + (r & 3);
+                    const int col = c0 + 32 * j + col_l;
+                    cv[r] = row < p.m && col < p.n ? C[(int64_t)row * p.ldc + col] : CT(0);
+                }
+            }
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = r0 + 32 * i + 8 * (r >> 2) + row_l + (r & 3);
                 const int col = c0 + 32 * j + col_l;
                 if (row < p.m && col < p.n) {
+                    CT *c = C + (int64_t)row * p.ldc + col;
                     if constexpr (DT::INT) {
-                        int *c = (int *)p.C + (int64_t)row * p.ldc + col;
                         u32 v = (u32)p.ialpha * (u32)acc[i][j][r];
-                        if (p.ibeta != 0) v += (u32)p.ibeta * (u32)(*c);
+                        if (read_c) v += (u32)p.ibeta * (u32)cv[r];
                         *c = (int)v;
                     } else {
-                        float *c = (float *)p.C + (int64_t)row * p.ldc + col;
                         float v = p.alpha * acc[i][j][r];
-                        if (p.beta != 0.0f) v = __builtin_fmaf(p.beta, *c, v);
+                        if (read_c) v = __builtin_fmaf(p.beta, cv[r], v);
                         *c = v;
                     }
                 }
             }
+        }
 }
 
 // ---------------------------------------------------------------------------
