@@ -137,8 +137,8 @@ typedef struct {
     int64_t chunk_tiles;  /* output tiles per published chunk, 0 = the number of    */
                           /* workgroups                                            */
     int64_t backlog_tiles;/* later chunks wait while this many published tiles are  */
-                          /* unclaimed, 0 = twice the number of workgroups; raised  */
-                          /* to workgroups + 17 at least                            */
+                          /* unclaimed, 0 = workgroups + 17 (the least it may be:   */
+                          /* smaller values are raised to it)                       */
 } serve_queue_config;
 
 /* Arguments: 1 cfg, 2 qcfg (NULL = defaults), 3 count, 4 reqs, 5 stats,

@@ -768,7 +768,7 @@ int run_queue(const serve_config &cfg, const serve_queue_config &qc, int64_t cou
     // the claimed word trails the claims by fewer than 16 + grid (it is
     // stored for every 16th tile, and the claiming workgroups' stores land in
     // any order), so a smaller backlog could read as full with every tile taken
-    const int64_t backlog = std::max<int64_t>(qc.backlog_tiles > 0 ? qc.backlog_tiles : 2 * (int64_t)grid,
+    const int64_t backlog = std::max<int64_t>(qc.backlog_tiles > 0 ? qc.backlog_tiles : (int64_t)grid + 17,
                                               (int64_t)grid + 17);
     QueueRes q;
     int rc = q.init(cfg, ring);
