@@ -706,6 +706,7 @@ struct DTile {
             __builtin_amdgcn_s_barrier();
         }
         if constexpr (W32) store_c32<DT, FM, FN>(p, acc, m0 + wm * WTM, n0 + wn * WTN, lane);
+        else if constexpr (NW == 8) store_c_batched<DT, FM, FN>(p, acc, m0 + wm * WTM, n0 + wn * WTN, lane);
         else store_c<DT, FM, FN>(p, acc, m0 + wm * WTM, n0 + wn * WTN, lane);
     }
 };

@@ -194,8 +194,11 @@ __global__ void __launch_bounds__(256, BODIES::MINB) grouped_kernel(const char *
     // Work stealing (thread 0's state): a workgroup draws from its own
     // group's queue, and once that has drained, from the following groups'
     // in turn; a drained queue costs one more claim, so every workgroup ends
-    // after at most L - 1 of them.
-    int src = g, drained = 0;
+    // after at most L - 1 of them.  Only launches of at least four tiles per
+    // workgroup steal: in a small launch nearly every workgroup would make
+    // its L - 1 claims at once, and those contended atomics cost more than
+    // the launch's work (a one-tile launch took 66 us instead of 25 us).
+    int src = g, drained = total >= 4 * (int)gridDim.x ? 0 : L;
     auto advance = [&](int nt) {
         while (nt >= total && ++drained < L) {
             src = src + 1 == L ? 0 : src + 1;

@@ -407,6 +407,49 @@ template <class DT, int FM, int FN>
 __device__ __forceinline__ void store_c(const GemmArgs &p, const typename AccOf<DT>::type (*acc)[FN],
                                         int r0, int c0, int lane)
 {
+    const int rbase = r0 + 4 * (lane >> 4);
+    const int cbase = c0 + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                // the FP64 MFMA interleaves its rows: register r of lane l is
+                // row l/16 + 4r (measured with identity operands)
+                const int row = DT::GES == 8 ? r0 + 16 * i + (lane >> 4) + 4 * r : rbase + 16 * i + r;
+                const int col = cbase + 16 * j;
+                if (row < p.m && col < p.n) {
+                    if constexpr (DT::INT) {
+                        int *c = (int *)p.C + (int64_t)row * p.ldc + col;
+                        u32 v = (u32)p.ialpha * (u32)acc[i][j][r];
+                        if (p.ibeta != 0) v += (u32)p.ibeta * (u32)(*c);
+                        *c = (int)v;
+                    } else if constexpr (DT::GES == 8) {
+                        double *c = (double *)p.C + (int64_t)row * p.ldc + col;
+                        double v = p.dalpha * acc[i][j][r];
+                        if (p.dbeta != 0.0) v = __builtin_fma(p.dbeta, *c, v);
+                        *c = v;
+                    } else {
+                        float *c = (float *)p.C + (int64_t)row * p.ldc + col;
+                        float v = p.alpha * acc[i][j][r];
+                        if (p.beta != 0.0f) v = __builtin_fmaf(p.beta, *c, v);
+                        *c = v;
+                    }
+                }
+            }
+}
+
+// The same epilogue with each row block's C values read before any of them
+// is written, so with beta != 0 the loads issue together (a store to C must
+// otherwise complete before the next load of C: the two may alias).  Twice
+// the code of store_c: used by the large single-GEMM tiles, where beta = 1
+// costs 2% of an 8192^3 FP32 product with store_c; in the grouped kernels
+// the larger code made every launch slower.
+template <class DT, int FM, int FN>
+__device__ __forceinline__ void store_c_batched(const GemmArgs &p, const typename AccOf<DT>::type (*acc)[FN],
+                                        int r0, int c0, int lane)
+{
     typedef typename std::conditional<DT::INT, int, typename std::conditional<DT::GES == 8, double, float>::type>::type CT;
     const int rbase = r0 + 4 * (lane >> 4);
     const int cbase = c0 + (lane & 15);
