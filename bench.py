@@ -127,7 +127,7 @@ def cpu_baseline(target_s=20.0):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU: --gpus must be 1"}))
         sys.exit(2)
     import torch
 
