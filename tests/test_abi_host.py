@@ -251,3 +251,27 @@ def test_shipped_tuning_table_names_existing_configurations():
         assert all(4 <= e[b] <= 12 for b in ("bm", "bn", "bk")), e
     assert seen == {(kc, tr) for kc in family for tr in range(4)}
     assert grouped >= {6}
+
+
+def test_config_mfma_form():
+    """gemm_config_mfma: 32 for the 32x32-block tiles (BF16, FP16, FP8, INT8
+    direct tiles and the x3/x6 packed split built on the BF16 ones), 16 for
+    every other configuration; negative for a bad dtype or id."""
+    L = mg.lib()
+    w32 = {}
+    for dt in range(mg.GEMM_NUM_DTYPES):
+        n = mg.num_configs(dt)
+        forms = [L.gemm_config_mfma(dt, i) for i in range(n)]
+        assert set(forms) <= {16, 32}, (dt, forms)
+        w32[dt] = [i for i, f in enumerate(forms) if f == 32]
+        for i in w32[dt]:
+            info = mg.config_info(dt, i)
+            assert info["mr"] % 32 == 0 and info["nr"] % 32 == 0, (dt, i, info)
+            assert info["staging"] in ("direct", "packed"), (dt, i, info)
+    for dt in (mg.GEMM_BF16, mg.GEMM_F16, mg.GEMM_F8E4M3, mg.GEMM_I8):
+        assert len(w32[dt]) >= 4, mg.DTYPE_NAMES[dt]
+    for dt in (mg.GEMM_F32, mg.GEMM_F64, mg.GEMM_I16, mg.GEMM_I32):
+        assert not w32[dt], mg.DTYPE_NAMES[dt]
+    assert L.gemm_config_mfma(99, 0) == -1
+    assert L.gemm_config_mfma(mg.GEMM_BF16, -1) == -2
+    assert L.gemm_config_mfma(mg.GEMM_BF16, mg.num_configs(mg.GEMM_BF16)) == -2
