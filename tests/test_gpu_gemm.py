@@ -378,6 +378,9 @@ def test_fp32_sweep_sampled(shape, beta):
                                    mg.GEMM_F16, mg.GEMM_F8E4M3],
                          ids=lambda d: mg.DTYPE_NAMES[d])
 @pytest.mark.parametrize("dist", ["normal", "badly_scaled"])
+# badly scaled FP16 inputs overflow on conversion (the case this test records)
+@pytest.mark.filterwarnings("ignore:overflow encountered in cast:RuntimeWarning")
+@pytest.mark.filterwarnings("ignore:invalid value encountered in subtract:RuntimeWarning")
 def test_precision_8192_sampled(dtype, dist):
     c = Case(dtype, "N", "N", 8192, 8192, 8192, 1.0, 0.0, dist=dist, seed=3)
     r = run_case(c, sample=_sample(8192, 8192, 128))

@@ -117,6 +117,7 @@ def test_scaled_special_cases():
     assert torch.equal(C1, 2 * C0) and torch.equal(C2, 3 * C0)
 
 
+@pytest.mark.filterwarnings("ignore:overflow encountered in cast:RuntimeWarning")
 def test_unscaled_fp16_overflows_where_scaled_does_not():
     # the reason for the scaled path: badly scaled data overflow binary16
     m, n, k = 96, 80, 128
