@@ -367,6 +367,35 @@ int gemm_force_config(int dtype, int id, int order);
 int gemm_last_config(int64_t out[4]);
 
 /*
+ * Debug aids (no part of the paper's method: checks that every tile writes
+ * its part of C).
+ *   Environment, read by gemm_init:
+ *     MGEMM_FORCE_CFG=dtype:id[:order][,dtype:id[:order]...] pins
+ *       configuration `id` (raster order `order`, default 0) for the dtype
+ *       (codes as in gemm_dtype) on every thread that has no pin of its own
+ *       (gemm_force_config); entries that do not parse, and ids the dtype
+ *       does not have, are ignored.
+ *     MGEMM_DEBUG (set, and not "0"): every gemm() / gemm_noalloc() call with
+ *       beta = 0 that runs a product kernel first fills the m x n block of C
+ *       with a sentinel (the NaN 0x7FC0DEAD; FP64 0x7FF8DEADDEADDEAD; int32 C
+ *       the same 32 bits), then counts the block's sentinel elements after
+ *       the product, so an element the product left unwritten is counted (as
+ *       is a computed value with exactly those bits).  Two extra kernels per
+ *       call, on the call's stream; nothing is counted for grouped launches.
+ *   gemm_debug_count(C, m, n, ldc, dtype): enqueue the same count, on the
+ *     calling thread's stream, for any m x n block of C (row-major, leading
+ *     dimension ldc, element type of dtype's C).  Returns -i for an invalid
+ *     i-th argument.
+ *   gemm_debug_unwritten(): synchronise the calling thread's stream and
+ *     return the count accumulated on the current device since the last
+ *     call (which resets it to 0); on failure minus a GEMM_E_* code.
+ * Both need gemm_init on the current device (GEMM_E_NOINIT otherwise, as
+ * -GEMM_E_NOINIT from gemm_debug_unwritten).
+ */
+int gemm_debug_count(const void *C, int64_t m, int64_t n, int64_t ldc, int dtype);
+int64_t gemm_debug_unwritten(void);
+
+/*
  * Autotuner (paper section 8.4, "In search of the best micro-kernel": a
  * search over micro-kernel shapes of a few dozen experiments).  For every
  * (m, n, k) in `shapes` (3*count int64) it times each compiled configuration

@@ -127,6 +127,10 @@ def lib():
     L.gemm_force_config.restype = _INT
     L.gemm_last_config.argtypes = [ctypes.POINTER(_I64)]
     L.gemm_last_config.restype = _INT
+    L.gemm_debug_count.argtypes = [ctypes.c_void_p, _I64, _I64, _I64, _INT]
+    L.gemm_debug_count.restype = _INT
+    L.gemm_debug_unwritten.argtypes = []
+    L.gemm_debug_unwritten.restype = _I64
     L.gemm_tune.argtypes = [_INT, _I64, ctypes.POINTER(_I64), _INT, ctypes.c_char_p]
     L.gemm_tune_pruned.argtypes = [_INT, _I64, ctypes.POINTER(_I64), _INT, ctypes.c_char_p, _INT]
     L.gemm_tune_pruned.restype = _INT
@@ -398,6 +402,19 @@ def config_supports(dtype: int, cfg: int, transA: str, transB: str, vec: bool = 
 
 def force_config(dtype: int, cfg: int, order: int = 0) -> None:
     _check(lib().gemm_force_config(int(dtype), int(cfg), int(order)), "gemm_force_config")
+
+
+def debug_count(C, m: int, n: int, ldc: int, dtype: int) -> None:
+    """Enqueue a count of the debug sentinel in the m x n block of C."""
+    _check(lib().gemm_debug_count(_ptr(C), m, n, ldc, int(dtype)), "gemm_debug_count")
+
+
+def debug_unwritten() -> int:
+    """Sentinel elements counted on this device since the last call (resets it)."""
+    v = int(lib().gemm_debug_unwritten())
+    if v < 0:
+        _check(-v, "gemm_debug_unwritten")
+    return v
 
 
 def last_config() -> dict:

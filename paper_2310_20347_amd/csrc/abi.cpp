@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -30,6 +31,28 @@ static bool g_table_loaded = false;
 DevState g_dev[kMaxDevices];
 std::map<TuneKey, TuneVal> g_table;
 thread_local Tls t_tls;
+
+// Process-wide defaults read from the environment by gemm_init:
+// MGEMM_FORCE_CFG pins a configuration per kernel class (a thread's own pin,
+// gemm_force_config, takes precedence); MGEMM_DEBUG turns on the sentinel
+// fill and count around every beta = 0 product.
+// (The environment's pin is held as id + 1, so that the zero-initialised
+// state, before any gemm_init, pins nothing.)
+static std::atomic<int> g_env_pin[K_NUM];
+static std::atomic<int> g_env_pin_order[K_NUM];
+static std::atomic<bool> g_debug{false};
+
+// The configuration pinned for a class: the thread's, else the environment's
+// (id < 0: none).
+static void pinned(int kclass, int &id, int &order)
+{
+    id = t_tls.force_id[kclass];
+    order = t_tls.force_order[kclass];
+    if (id < 0) {
+        id = g_env_pin[kclass].load(std::memory_order_relaxed) - 1;
+        order = g_env_pin_order[kclass].load(std::memory_order_relaxed);
+    }
+}
 
 Tls::Tls()
 {
@@ -427,9 +450,11 @@ static void heuristic(int kclass, int trans, int64_t m, int64_t n, int64_t k, in
 void select_config(int kclass, int trans, int64_t m, int64_t n, int64_t k, int cus, int &id,
                    int &order, int &group)
 {
-    if (t_tls.force_id[kclass] >= 0 && t_tls.force_id[kclass] < (int)g_by_class[kclass].size()) {
-        id = t_tls.force_id[kclass];
-        order = t_tls.force_order[kclass];
+    int pin, pin_order;
+    pinned(kclass, pin, pin_order);
+    if (pin >= 0 && pin < (int)g_by_class[kclass].size()) {
+        id = pin;
+        order = pin_order;
         group = t_tls.force_group > 0 ? t_tls.force_group : 8;
         return;
     }
@@ -684,7 +709,9 @@ int plan_gemm(int dtype, char ta, char tb, int64_t m, int64_t n, int64_t k, doub
         // choice gives way to the model's best among the configurations that
         // have one; a forced one to the class's first configuration, which
         // carries every element-wise staging variant
-        const bool forced = t_tls.force_id[kclass] >= 0;
+        int pin, pin_order;
+        pinned(kclass, pin, pin_order);
+        const bool forced = pin >= 0;
         cfg_id = forced ? 0 : model_best(kclass, trans, vec, m, n, k, cus);
         reg = g_by_class[kclass][cfg_id];
         if (!g_cfgs[reg].func[trans][vec ? 1 : 0]) {
@@ -766,8 +793,12 @@ int gemm_ws(char transA, char transB, int64_t m, int64_t n, int64_t k, double al
         t_tls.force_id[kclass] = saved;
         if (run < 0) return GEMM_E_UNSUPPORTED;
     }
+    const bool debug = g_debug.load(std::memory_order_relaxed) && d->debug_count && beta == 0.0;
+    const int es = dtype == GEMM_F64 ? 8 : 4;
+    if (debug) launch_debug_fill(C, ldc, m, n, es, s);
     rc = launch_gemm(g_cfgs[run], trans, vec, a, s, w);
     if (rc == kPackUnavailable) rc = GEMM_E_UNSUPPORTED;   // packing pass not built for this case
+    if (rc == GEMM_OK && debug) launch_debug_count(C, ldc, m, n, es, d->debug_count, s);
     if (rc == GEMM_OK) {
         t_tls.last[0] = dtype;
         t_tls.last[1] = cfg;
@@ -775,6 +806,76 @@ int gemm_ws(char transA, char transB, int64_t m, int64_t n, int64_t k, double al
         t_tls.last[3] = a.terms;
     }
     return rc;
+}
+
+// The debug counter of a device (allocated once, zeroed; outside any capture).
+static int debug_device_init(DevState *d)
+{
+    std::lock_guard<std::mutex> g(g_mu);
+    if (d->debug_count) return GEMM_OK;
+    unsigned long long *p = nullptr;
+    hipError_t e = hipMalloc((void **)&p, sizeof *p);
+    if (e == hipSuccess) e = hipMemset(p, 0, sizeof *p);
+    if (e != hipSuccess) {
+        if (p) (void)hipFree(p);
+        t_tls.hip_err = (int)e;
+        return GEMM_E_HIP;
+    }
+    d->debug_count = p;
+    return GEMM_OK;
+}
+
+// The kernel class whose configurations a query about dtype lists (the x3
+// split: its three-term class).
+static int class_for_query(int dtype)
+{
+    if (dtype == GEMM_F32_BF16X3) return K_SPLIT2;
+    return kclass_of(dtype, 0);
+}
+
+// MGEMM_DEBUG (non-empty and not "0") and MGEMM_FORCE_CFG, a comma-separated
+// list of dtype:id[:order] (dtype codes as in mgemm.h; entries that do not
+// parse or name no configuration are ignored).
+static void apply_env_settings()
+{
+    const char *dbg = std::getenv("MGEMM_DEBUG");
+    g_debug.store(dbg && *dbg && std::strcmp(dbg, "0") != 0);
+    int pin[K_NUM], pin_order[K_NUM];
+    for (int c = 0; c < K_NUM; ++c) {
+        pin[c] = -1;
+        pin_order[c] = 0;
+    }
+    const char *v = std::getenv("MGEMM_FORCE_CFG");
+    while (v && *v) {
+        char *end = nullptr;
+        const long dt = std::strtol(v, &end, 10);
+        long id = -1, order = 0;
+        bool ok = end != v && *end == ':';
+        if (ok) {
+            v = end + 1;
+            id = std::strtol(v, &end, 10);
+            ok = end != v;
+            if (ok && *end == ':') {
+                v = end + 1;
+                order = std::strtol(v, &end, 10);
+                ok = end != v && (order == 0 || order == 1);
+            }
+        }
+        if (ok && dt >= 0 && dt < GEMM_NUM_DTYPES && id >= 0) {
+            int classes[2] = {class_for_query((int)dt), dt == GEMM_F32_BF16X3 ? K_SPLIT3 : -1};
+            for (int c : classes)
+                if (c >= 0 && id < (long)g_by_class[c].size()) {
+                    pin[c] = (int)id;
+                    pin_order[c] = (int)order;
+                }
+        }
+        const char *comma = std::strchr(end ? end : v, ',');
+        v = comma ? comma + 1 : nullptr;
+    }
+    for (int c = 0; c < K_NUM; ++c) {
+        g_env_pin_order[c].store(pin_order[c], std::memory_order_relaxed);
+        g_env_pin[c].store(pin[c] + 1, std::memory_order_relaxed);
+    }
 }
 
 }  // namespace mg
@@ -838,6 +939,9 @@ int gemm_init(const char *tune_table_path)
     if (rc != GEMM_OK) return rc;
     rc = scratch_device_init(d->device);
     if (rc != GEMM_OK) return rc;
+    rc = debug_device_init(d);
+    if (rc != GEMM_OK) return rc;
+    apply_env_settings();
     const hipStream_t s = t_tls.stream;
     rc = reserve_workspace(d, s, (size_t)env_bytes("MGEMM_WORKSPACE_BYTES", kDefaultWorkspace), 0);
     if (rc != GEMM_OK) return rc;
@@ -850,6 +954,10 @@ void gemm_shutdown(void)
     for (int i = 0; i < kMaxDevices; ++i) {
         grouped_device_free(&g_dev[i]);
         free_workspaces(&g_dev[i]);
+        if (g_dev[i].debug_count) {
+            (void)hipFree(g_dev[i].debug_count);
+            g_dev[i].debug_count = nullptr;
+        }
     }
 }
 
@@ -917,12 +1025,6 @@ const char *gemm_strerror(int code)
 }
 
 int gemm_last_hip_error(void) { return t_tls.hip_err; }
-
-static int class_for_query(int dtype)
-{
-    if (dtype == GEMM_F32_BF16X3) return K_SPLIT2;
-    return kclass_of(dtype, 0);
-}
 
 int gemm_num_configs(int dtype)
 {
@@ -1002,6 +1104,44 @@ int gemm_force_config(int dtype, int id, int order)
         t_tls.force_order[c] = order;
     }
     return GEMM_OK;
+}
+
+int gemm_debug_count(const void *C, int64_t m, int64_t n, int64_t ldc, int dtype)
+{
+    if (!C && m > 0 && n > 0) return -1;
+    if (m < 0) return -2;
+    if (n < 0) return -3;
+    if (ldc < std::max<int64_t>(1, n)) return -4;
+    if (dtype < 0 || dtype >= GEMM_NUM_DTYPES) return -5;
+    DevState *d = nullptr;
+    int rc = device_state(&d);
+    if (rc != GEMM_OK) return rc;
+    if (!d->debug_count) return GEMM_E_NOINIT;
+    if (m == 0 || n == 0) return GEMM_OK;
+    launch_debug_count(C, ldc, m, n, dtype == GEMM_F64 ? 8 : 4, d->debug_count, t_tls.stream);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        t_tls.hip_err = (int)e;
+        return GEMM_E_HIP;
+    }
+    return GEMM_OK;
+}
+
+int64_t gemm_debug_unwritten(void)
+{
+    DevState *d = nullptr;
+    int rc = device_state(&d);
+    if (rc != GEMM_OK) return -rc;
+    if (!d->debug_count) return -GEMM_E_NOINIT;
+    unsigned long long v = 0;
+    hipError_t e = hipStreamSynchronize(t_tls.stream);
+    if (e == hipSuccess) e = hipMemcpy(&v, d->debug_count, sizeof v, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemset(d->debug_count, 0, sizeof v);
+    if (e != hipSuccess) {
+        t_tls.hip_err = (int)e;
+        return -GEMM_E_HIP;
+    }
+    return (int64_t)v;
 }
 
 int gemm_last_config(int64_t out[4])

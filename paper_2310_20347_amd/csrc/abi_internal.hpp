@@ -32,6 +32,8 @@ struct DevState {
     // still be enqueuing work that reads them, so they are freed only at
     // gemm_shutdown (or gemm_release_workspace of their stream)
     std::vector<std::pair<std::pair<hipStream_t, int>, void *>> retired;
+    // debug mode: count of sentinel elements found (allocated by gemm_init)
+    unsigned long long *debug_count = nullptr;
 };
 
 // Internal status of launch_gemm: a packed configuration could not get its

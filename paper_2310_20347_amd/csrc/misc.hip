@@ -1,6 +1,6 @@
 // Small auxiliary kernels: C = beta*C (the alpha == 0 / k == 0 case of the
-// BLAS semantics), the split-K reduction and a deterministic operand fill
-// used by the tuner.
+// BLAS semantics), the split-K reduction, a deterministic operand fill used
+// by the tuner, and the debug mode's sentinel fill and count.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -39,6 +39,56 @@ __global__ void scale_f64_kernel(double *C, int64_t ldc, int m, int n, double be
         double *c = C + i * ldc + j;
         *c = beta == 0.0 ? 0.0 : beta * *c;   // beta == 0: C is not read
     }
+}
+
+// Debug mode: the m x n block of C is filled with a sentinel (a NaN with a
+// payload of its own; for int32 C the same bits) before a beta = 0 product,
+// and counted after it, so elements the product left unwritten are found.
+constexpr unsigned kSentinel32 = 0x7FC0DEADu;
+constexpr unsigned long long kSentinel64 = 0x7FF8DEADDEADDEADull;
+
+__global__ void debug_fill_kernel(char *C, int64_t ldc, int64_t m, int64_t n, int es)
+{
+    const int64_t total = m * n;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / n, j = t - i * n;
+        if (es == 8) ((unsigned long long *)C)[i * ldc + j] = kSentinel64;
+        else ((unsigned *)C)[i * ldc + j] = kSentinel32;
+    }
+}
+
+__global__ void debug_count_kernel(const char *C, int64_t ldc, int64_t m, int64_t n, int es,
+                                   unsigned long long *count)
+{
+    const int64_t total = m * n;
+    unsigned long long found = 0;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / n, j = t - i * n;
+        if (es == 8) found += ((const unsigned long long *)C)[i * ldc + j] == kSentinel64;
+        else found += ((const unsigned *)C)[i * ldc + j] == kSentinel32;
+    }
+    if (found) atomicAdd(count, found);
+}
+
+static int64_t debug_blocks(int64_t total)
+{
+    int64_t blocks = (total + 255) / 256;
+    return blocks > 4096 ? 4096 : (blocks < 1 ? 1 : blocks);
+}
+
+void launch_debug_fill(void *C, int64_t ldc, int64_t m, int64_t n, int es, hipStream_t s)
+{
+    hipLaunchKernelGGL(debug_fill_kernel, dim3((unsigned)debug_blocks(m * n)), dim3(256), 0, s,
+                       (char *)C, ldc, m, n, es);
+}
+
+void launch_debug_count(const void *C, int64_t ldc, int64_t m, int64_t n, int es,
+                        unsigned long long *count, hipStream_t s)
+{
+    hipLaunchKernelGGL(debug_count_kernel, dim3((unsigned)debug_blocks(m * n)), dim3(256), 0, s,
+                       (const char *)C, ldc, m, n, es, count);
 }
 
 void launch_scale(void *C, int64_t ldc, int m, int n, double beta, int elem, hipStream_t s)

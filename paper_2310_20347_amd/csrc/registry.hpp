@@ -70,6 +70,12 @@ void register_f64(std::vector<KernelCfg> &out);
 // Plain C = beta * C (alpha == 0 or k == 0); elem: 0 float, 1 int32, 2 double.
 void launch_scale(void *C, int64_t ldc, int m, int n, double beta, int elem, hipStream_t s);
 
+// Debug mode: fill the m x n block of C with the sentinel (es: element bytes,
+// 4 or 8), and add the number of sentinel elements of the block to *count.
+void launch_debug_fill(void *C, int64_t ldc, int64_t m, int64_t n, int es, hipStream_t s);
+void launch_debug_count(const void *C, int64_t ldc, int64_t m, int64_t n, int es,
+                        unsigned long long *count, hipStream_t s);
+
 // Split-K reduction: C = alpha * sum_{s < S} P[s] + beta * C, slices summed in
 // order (P: S partial m x n tiles, row stride n, float or int32).
 void launch_splitk_reduce(const void *P, int S, void *C, int64_t ldc, int m, int n,

@@ -275,3 +275,21 @@ def test_config_mfma_form():
     assert L.gemm_config_mfma(99, 0) == -1
     assert L.gemm_config_mfma(mg.GEMM_BF16, -1) == -2
     assert L.gemm_config_mfma(mg.GEMM_BF16, mg.num_configs(mg.GEMM_BF16)) == -2
+
+
+def test_debug_count_validates_before_the_device():
+    L = mg.lib()
+    L.gemm_debug_count.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                   ctypes.c_int64, ctypes.c_int]
+    L.gemm_debug_count.restype = ctypes.c_int
+    assert L.gemm_debug_count(None, 4, 5, 5, mg.GEMM_F32) == -1
+    assert L.gemm_debug_count(0x1000, -1, 5, 5, mg.GEMM_F32) == -2
+    assert L.gemm_debug_count(0x1000, 4, -1, 5, mg.GEMM_F32) == -3
+    assert L.gemm_debug_count(0x1000, 4, 5, 4, mg.GEMM_F32) == -4
+    assert L.gemm_debug_count(0x1000, 4, 5, 5, 99) == -5
+    assert L.gemm_debug_count(None, 0, 5, 5, 99) == -5   # C unused when the block is empty
+    import torch
+    if not torch.cuda.is_available():
+        assert L.gemm_debug_count(0x1000, 4, 5, 5, mg.GEMM_F32) == 3   # no device
+        L.gemm_debug_unwritten.restype = ctypes.c_int64
+        assert L.gemm_debug_unwritten() == -3
