@@ -74,3 +74,49 @@ def test_concurrent_threads_match_one_thread():
         t.join(timeout=120)
     assert not any(t.is_alive() for t in threads), "a thread did not finish"
     assert not errors, errors
+
+
+def test_concurrent_grouped_launches_match_one_thread():
+    """Grouped launches from several threads, each on its own stream (the
+    library's rotating descriptor slots are shared), equal the one-thread
+    launch bit for bit."""
+    import torch
+    mg.gemm_init(None)
+    g = torch.Generator().manual_seed(9)
+    shapes = [(37, 300, 64), (256, 128, 512), (16, 16, 16), (515, 97, 1024), (128, 640, 208),
+              (1000, 24, 96), (64, 64, 4096), (300, 300, 304)]
+    for dt in (mg.GEMM_I8, mg.GEMM_F32_BF16X3):
+        ops = [(m, n, k) + _operands(torch, g, dt, m, n, k) for m, n, k in shapes]
+
+        def problems(Cs):
+            return [mg.Problem("N", "N", m, n, k, one, A, k, B, n, zero, C, n)
+                    for (m, n, k, A, B, ct, one, zero), C in zip(ops, Cs)]
+
+        ref = [torch.zeros((m, n), dtype=ct, device="cuda") for m, n, k, A, B, ct, one, zero in ops]
+        mg.gemm_grouped(problems(ref), dt)
+        torch.cuda.synchronize()
+        errors = []
+
+        def worker(tid):
+            try:
+                s = torch.cuda.Stream()
+                Cs = [torch.full((m, n), -1, dtype=ct, device="cuda")
+                      for m, n, k, A, B, ct, one, zero in ops]
+                torch.cuda.synchronize()
+                batch = problems(Cs)
+                for it in range(ITERS):
+                    mg.gemm_grouped(batch, dt, stream=s)
+                s.synchronize()
+                for i, C in enumerate(Cs):
+                    if not torch.equal(C, ref[i]):
+                        errors.append(f"{mg.DTYPE_NAMES[dt]} thread {tid} problem {i} differs")
+            except Exception as e:  # reported below, with the thread
+                errors.append(f"{mg.DTYPE_NAMES[dt]} thread {tid}: {e!r}")
+
+        threads = [threading.Thread(target=worker, args=(t,)) for t in range(THREADS)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join(timeout=120)
+        assert not any(t.is_alive() for t in threads), "a thread did not finish"
+        assert not errors, errors
