@@ -195,8 +195,11 @@ typedef struct {
  * p returns -(1000*p + i) and nothing is launched.  Problems that gemm()
  * would quick-return are skipped.  Output regions of different problems
  * must not overlap.  Returns GEMM_E_WORKSPACE when count exceeds
- * gemm_grouped_capacity().  The staging slot is reused after the stream has
- * consumed it (an event guards reuse), so back-to-back calls are safe.
+ * gemm_grouped_capacity().  Calls rotate over a few library staging slots;
+ * a slot is reused only after the stream has consumed its previous table (an
+ * event guards reuse), so back-to-back calls are safe, and a call whose slot
+ * still has a copy in flight waits on the host for that copy.  Loops that
+ * must never wait, and graph capture, use the slots below.
  */
 int gemm_grouped(int64_t count, const gemm_problem *problems, int dtype);
 
